@@ -1,0 +1,294 @@
+"""The FP64 oracle checked against facts that do not come from the oracle itself."""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2411_13532_amd import workloads
+from tests import pins
+
+
+def chain(X, A, B, C):
+    return oracle.chain(X, A, B, C)
+
+
+def chain_ordered(X, A, B, C, order):
+    return oracle.chain(X, A, B, C, order=order)
+
+
+@pytest.mark.parametrize("pin", pins.ALL_CHAIN_PINS, ids=lambda p: p.__name__)
+def test_oracle_chain_pins(pin):
+    pin(chain)
+
+
+def test_oracle_bruteforce_pin():
+    pins.pin_bruteforce(chain, oracle.brute)
+
+
+def test_oracle_brute_is_the_definition():
+    # the C six-fold sum against Python loops written from the definition
+    rng = np.random.default_rng(1)
+    I, J = (2, 3, 2), (2, 2, 3)
+    X = rng.standard_normal(I)
+    A, B, C = (rng.standard_normal((J[n], I[n])) for n in range(3))
+    ref = np.zeros(J)
+    for j1, j2, j3 in itertools.product(*(range(j) for j in J)):
+        for i1, i2, i3 in itertools.product(*(range(i) for i in I)):
+            ref[j1, j2, j3] += A[j1, i1] * B[j2, i2] * C[j3, i3] * X[i1, i2, i3]
+    np.testing.assert_allclose(oracle.brute(X, A, B, C), ref, rtol=1e-14, atol=1e-15)
+
+
+def test_oracle_mode_order_pin():
+    pins.pin_mode_order(chain_ordered)
+
+
+def test_oracle_float32_input_is_exact_upcast():
+    p = workloads.random_problem((9, 10, 11), (3, 4, 5), seed=3, dtype=np.float32)
+    y32 = oracle.chain(p["X"], p["A"], p["B"], p["C"])
+    y64 = oracle.chain(p["X"].astype(np.float64), p["A"], p["B"], p["C"])
+    assert np.array_equal(y32, y64)
+    for order in itertools.permutations((1, 2, 3)):
+        y = oracle.chain(p["X"], p["A"], p["B"], p["C"], order=order)
+        assert pins.rel_fro(y, y64) < 1e-14
+
+
+def test_oracle_single_mode_product_matches_matrix_product():
+    # X x_n U is U @ (mode-n unfolding); numpy moveaxis builds the unfolding
+    rng = np.random.default_rng(4)
+    X = rng.standard_normal((4, 5, 6))
+    for mode, n in ((1, 4), (2, 5), (3, 6)):
+        U = rng.standard_normal((3, n))
+        out = oracle.mode_product(X, U, mode)
+        ref = np.moveaxis(np.tensordot(U, X, axes=([1], [mode - 1])), 0, mode - 1)
+        np.testing.assert_allclose(out, ref, rtol=1e-13, atol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# Planted mistakes: each broken chain must fail at least one pin.
+# ---------------------------------------------------------------------------
+def _mut_transposed_A(X, A, B, C):
+    # uses A^T where A is square, or fails on shape otherwise
+    if A.shape[0] != A.shape[1]:
+        A = np.resize(A.T, A.shape)
+    else:
+        A = A.T
+    return np.einsum("abc,ia,jb,kc->ijk", X, A, B, C)
+
+
+def _mut_reversed_index(X, A, B, C):
+    # contracts mode 3 against C with its column index reversed
+    return np.einsum("abc,ia,jb,kc->ijk", X, A, B, C[:, ::-1])
+
+
+def _mut_dropped_last_term(X, A, B, C):
+    return np.einsum("abc,ia,jb,kc->ijk", X[:, :, :-1], A, B, C[:, :-1])
+
+
+def _mut_sign(X, A, B, C):
+    Y = np.einsum("abc,ia,jb,kc->ijk", X, A, B, C)
+    Y[..., -1] *= -1
+    return Y
+
+
+def _mut_float32_intermediate(X, A, B, C):
+    t = np.einsum("abc,kc->abk", X, C).astype(np.float32).astype(np.float64)
+    return np.einsum("abk,ia,jb->ijk", t, A, B)
+
+
+@pytest.mark.parametrize("mutant", [_mut_transposed_A, _mut_reversed_index, _mut_dropped_last_term,
+                                    _mut_sign, _mut_float32_intermediate],
+                         ids=lambda m: m.__name__)
+def test_planted_mistakes_are_caught(mutant):
+    failures = 0
+    for pin in pins.ALL_CHAIN_PINS:
+        try:
+            pin(mutant)
+        except AssertionError:
+            failures += 1
+    assert failures > 0, f"{mutant.__name__} passed every pin"
+
+
+# ---------------------------------------------------------------------------
+# Thomas algorithm (Sec. 2.1) and the paper's compact scheme as a mode product
+# ---------------------------------------------------------------------------
+def test_thomas_matches_dense_solve():
+    rng = np.random.default_rng(5)
+    for n in (1, 2, 5, 33):
+        a, c = rng.standard_normal(n), rng.standard_normal(n)
+        b = 4.0 + np.abs(rng.standard_normal(n))
+        d = rng.standard_normal(n)
+        M = np.diag(b) + np.diag(a[1:], -1) + np.diag(c[:-1], 1)
+        np.testing.assert_allclose(oracle.thomas(a, b, c, d), np.linalg.solve(M, d), rtol=1e-12, atol=1e-14)
+
+
+def test_periodic_thomas_matches_dense_solve():
+    rng = np.random.default_rng(6)
+    for n in (3, 4, 17):
+        a, c = rng.standard_normal(n), rng.standard_normal(n)
+        b = 4.0 + np.abs(rng.standard_normal(n))
+        d = rng.standard_normal(n)
+        M = np.diag(b) + np.diag(a[1:], -1) + np.diag(c[:-1], 1)
+        M[0, n - 1] = a[0]
+        M[n - 1, 0] = c[n - 1]
+        np.testing.assert_allclose(oracle.thomas(a, b, c, d, periodic=True), np.linalg.solve(M, d),
+                                   rtol=1e-12, atol=1e-14)
+
+
+def test_compact6_eigen_relation_1d():
+    # D sin(m x) = k'(m) cos(m x) on periodic grids (Eq. (cfds))
+    for n in (16, 32, 64):
+        D = pins.compact6_derivative_matrix(n)
+        x = np.arange(n) * 2 * np.pi / n
+        for m in (1, 3, n // 4):
+            lhs = D @ np.sin(m * x)
+            rhs = pins.compact6_modified_wavenumber(m, n) * np.cos(m * x)
+            assert np.max(np.abs(lhs - rhs)) < 1e-12 * max(1.0, np.max(np.abs(rhs)))
+    # low modes approach the exact derivative (sixth-order accuracy)
+    n = 64
+    assert abs(pins.compact6_modified_wavenumber(1, n) - 1.0) < 1e-9
+
+
+def test_periodic_thomas_applies_compact6_along_fibers():
+    # the paper's solver (periodic Thomas on A_c u' = B_c u) per mode-2 fiber
+    # equals the dense mode product with D = A_c^-1 B_c
+    n = 24
+    h = 2 * np.pi / n
+    alpha, _, _ = pins.compact6_coefficients()
+    Ac, Bc = pins.compact6_periodic_matrices(n, h)
+    D = np.linalg.solve(Ac, Bc)
+    rng = np.random.default_rng(7)
+    X = rng.standard_normal((5, n, 6))
+    ref = oracle.mode_product(X, D, 2)
+    out = np.empty_like(X)
+    band = np.full(n, alpha)
+    ones = np.ones(n)
+    for i1 in range(X.shape[0]):
+        for i3 in range(X.shape[2]):
+            out[i1, :, i3] = oracle.thomas(band, ones, band, Bc @ X[i1, :, i3], periodic=True)
+    np.testing.assert_allclose(out, ref, rtol=1e-12, atol=1e-12)
+
+
+def test_thomas_applies_nonperiodic_compact6_along_mode1():
+    n = 20
+    h = 1.0 / (n - 1)
+    Ac, Bc = pins.compact6_nonperiodic_matrices(n, h)
+    D = np.linalg.solve(Ac, Bc)
+    a = np.concatenate([[0.0], np.diag(Ac, -1)])
+    c = np.concatenate([np.diag(Ac, 1), [0.0]])
+    b = np.diag(Ac).copy()
+    rng = np.random.default_rng(8)
+    X = rng.standard_normal((n, 4, 3))
+    ref = oracle.mode_product(X, D, 1)
+    out = np.empty_like(X)
+    for i2 in range(4):
+        for i3 in range(3):
+            out[:, i2, i3] = oracle.thomas(a, b, c, Bc @ X[:, i2, i3])
+    np.testing.assert_allclose(out, ref, rtol=1e-11, atol=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# Backward oracle
+# ---------------------------------------------------------------------------
+def test_adjoint_identity():
+    rng = np.random.default_rng(9)
+    I, J = (6, 7, 8), (3, 5, 4)
+    X = rng.standard_normal(I)
+    A, B, C = (rng.standard_normal((J[n], I[n])) for n in range(3))
+    G = rng.standard_normal(J)
+    dX, _, _, _ = oracle.backward(G, X, A, B, C)
+    lhs = float(np.sum(oracle.chain(X, A, B, C) * G))
+    rhs = float(np.sum(X * dX))
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs) + 1e-13
+
+
+def test_backward_matches_einsum_gradients():
+    rng = np.random.default_rng(10)
+    I, J = (5, 6, 4), (3, 2, 4)
+    X = rng.standard_normal(I)
+    A, B, C = (rng.standard_normal((J[n], I[n])) for n in range(3))
+    G = rng.standard_normal(J)
+    dX, dA, dB, dC = oracle.backward(G, X, A, B, C)
+    np.testing.assert_allclose(dX, np.einsum("ijk,ia,jb,kc->abc", G, A, B, C), rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(dA, np.einsum("ijk,abc,jb,kc->ia", G, X, B, C), rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(dB, np.einsum("ijk,abc,ia,kc->jb", G, X, A, C), rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(dC, np.einsum("ijk,abc,ia,jb->kc", G, X, A, B), rtol=1e-12, atol=1e-13)
+
+
+def test_backward_central_differences_fd_variant():
+    """Full central-difference gradient of L = 1/2||Y-T||^2 on the 16^3 variant.
+    L is quadratic along every single coordinate, so the central difference has
+    no truncation error, only rounding (about eps*L/h)."""
+    p = workloads.fd_variant()
+    X, A, B, C, T = p["X"], p["A"], p["B"], p["C"], p["T"]
+    G = oracle.chain(X, A, B, C) - T
+    grads = oracle.backward(G, X, A, B, C)
+    h = 1e-6
+    L0 = oracle.loss(X, A, B, C, T)
+    args = [X, A, B, C]
+    for which, g in enumerate(grads):
+        base = args[which]
+        fd = np.empty(base.size)
+        flat = base.ravel()
+        for k in range(base.size):
+            old = flat[k]
+            flat[k] = old + h
+            lp = oracle.loss(*args, T)
+            flat[k] = old - h
+            lm = oracle.loss(*args, T)
+            flat[k] = old
+            fd[k] = (lp - lm) / (2 * h)
+        err = np.linalg.norm(fd - g.ravel()) / np.linalg.norm(g.ravel())
+        assert err < 1e-6, (which, err, L0)
+
+
+# ---------------------------------------------------------------------------
+# Batched oracle
+# ---------------------------------------------------------------------------
+def test_batched_oracle_matches_per_cuboid_brute():
+    dims = [(2, 3, 4, 3, 2, 1), (1, 1, 1, 1, 1, 1), (3, 3, 3, 3, 3, 3), (4, 2, 1, 2, 5, 3)]
+    p = workloads.random_batched(dims, seed=11)
+    Y = oracle.batched(p["dims"], p["X"], p["A"], p["B"], p["C"])
+    ox = oa = ob = oc = oy = 0
+    for d in dims:
+        I1, I2, I3, J1, J2, J3 = d
+        X = p["X"][ox:ox + I1 * I2 * I3].reshape(I1, I2, I3)
+        A = p["A"][oa:oa + J1 * I1].reshape(J1, I1)
+        B = p["B"][ob:ob + J2 * I2].reshape(J2, I2)
+        C = p["C"][oc:oc + J3 * I3].reshape(J3, I3)
+        ref = oracle.brute(X, A, B, C)
+        got = Y[oy:oy + J1 * J2 * J3].reshape(J1, J2, J3)
+        np.testing.assert_allclose(got, ref, rtol=1e-13, atol=1e-14)
+        ox += I1 * I2 * I3; oa += J1 * I1; ob += J2 * I2; oc += J3 * I3; oy += J1 * J2 * J3
+    assert oy == Y.size
+
+
+# ---------------------------------------------------------------------------
+# Workload generators (no arithmetic of the method; shapes and statistics)
+# ---------------------------------------------------------------------------
+def test_workload_c1_shapes_and_determinism():
+    p = workloads.dense("c1_f64_64_16")
+    q = workloads.dense("c1_f64_64_16")
+    assert p["X"].shape == (64, 64, 64) and p["A"].shape == (16, 64)
+    assert np.array_equal(p["X"], q["X"]) and np.array_equal(p["C"], q["C"])
+    # N(0, 1/64): standard deviation 1/8
+    assert abs(np.std(np.concatenate([p["A"].ravel(), p["B"].ravel(), p["C"].ravel()])) - 0.125) < 0.01
+
+
+def test_orthonormal_rows_generator():
+    rng = np.random.default_rng(0)
+    Q = workloads.orthonormal_rows(rng, 8, 40)
+    np.testing.assert_allclose(Q @ Q.T, np.eye(8), atol=1e-14)
+
+
+def test_c1_oracle_gaussian_statistics():
+    # For X ~ N(0,1) i.i.d. and factors with N(0,1/I) entries, E[Y^2] = product of
+    # the squared row norms' expectation, i.e. about 1; the sample mean square of
+    # 16^3 entries is 1 within a few percent.
+    p = workloads.dense("c1_f64_64_16")
+    Y = oracle.chain(p["X"], p["A"], p["B"], p["C"])
+    assert Y.shape == (16, 16, 16)
+    ms = float(np.mean(Y ** 2))
+    expected = float(np.mean(np.sum(p["A"] ** 2, 1))) * float(np.mean(np.sum(p["B"] ** 2, 1))) \
+        * float(np.mean(np.sum(p["C"] ** 2, 1)))
+    assert abs(ms / expected - 1.0) < 0.25
