@@ -1,0 +1,209 @@
+/*
+ * ttm.h -- C interface of libttm, the MI355X (gfx950) library for the chain of
+ * mode-n tensor-times-matrix products on dense 3-way tensors.
+ *
+ * Operator (mode-n product, the directional operator the paper applies along
+ * one direction of a 3D field, Sec. 4.2 Eq. (cfds), here with one dense factor
+ * per mode):
+ *
+ *     Y = X x1 A x2 B x3 C,
+ *     Y[j1,j2,j3] = sum_{i1,i2,i3} A[j1,i1] * B[j2,i2] * C[j3,i3] * X[i1,i2,i3]
+ *
+ * Layout.  Every tensor is dense and row-major (C order):
+ *     X  [I1][I2][I3]  (i3 contiguous)     Y  [J1][J2][J3]
+ *     A  [J1][I1]      B  [J2][I2]         C  [J3][I3]
+ * No mode unfolding is ever materialised: each contraction reads its operand
+ * through strides, and operand transposes happen in registers or LDS.
+ *
+ * Memory.  Every tensor pointer is a device pointer owned by the caller; the
+ * library never allocates or frees caller tensors.  Scratch space comes from a
+ * caller-owned device workspace whose size the *_workspace_size queries give.
+ * The only library-owned memory is a batched plan (host and device metadata),
+ * created by ttm_batched_plan_create and freed by ttm_batched_plan_destroy.
+ *
+ * Ordering.  Every compute call is asynchronous and ordered on the caller's
+ * HIP stream (passed as an opaque pointer; NULL is the null stream).  The
+ * compute calls neither synchronise nor allocate, so they may be captured into
+ * a HIP graph.  A device fault surfaces at the caller's next synchronisation.
+ *
+ * Errors.  Arguments are validated before anything is launched; on error a
+ * negative ttm_status is returned and nothing has been written.
+ *
+ * Threads.  Calls are re-entrant; a plan is immutable after creation except
+ * for its autotuned choice, which ttm_batched_autotune sets.
+ */
+#ifndef TTM_H
+#define TTM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TTM_OK = 0,
+    TTM_ERR_INVALID_ARG = -1,  /* null pointer, non-positive size, bad alignment */
+    TTM_ERR_UNSUPPORTED = -2,  /* dtype/math combination or size not provided */
+    TTM_ERR_WORKSPACE = -3,    /* workspace missing or smaller than required */
+    TTM_ERR_ALIAS = -4,        /* an output overlaps an input */
+    TTM_ERR_HIP = -5           /* the HIP runtime reported an error */
+} ttm_status;
+
+typedef enum { TTM_F64 = 0, TTM_F32 = 1, TTM_BF16 = 2 } ttm_dtype;
+
+/*
+ * Arithmetic of a call.
+ *  F64    : double products, double accumulation.
+ *  F32    : float products, float accumulation (FP32 matrix cores).
+ *  BF16   : every operand rounded to bfloat16 (round to nearest even) before
+ *           each product, float accumulation; intermediates are re-rounded to
+ *           bfloat16 when they become the next product's operand.
+ *  BF16X3 : every float operand v is split into hi = rne_bf16(v) and
+ *           lo = rne_bf16(v - hi); a product is formed as hi*hi' + hi*lo' +
+ *           lo*hi' on bfloat16 matrix cores with float accumulation, and
+ *           intermediates stay float and are split again.  Reaches float-level
+ *           accuracy at bfloat16 matrix-core rates.
+ */
+typedef enum { TTM_MATH_F64 = 0, TTM_MATH_F32 = 1, TTM_MATH_BF16 = 2, TTM_MATH_BF16X3 = 3 } ttm_math;
+
+/* Sizes of one chain: X is I[0] x I[1] x I[2], Y is J[0] x J[1] x J[2]. */
+typedef struct { int64_t I[3]; int64_t J[3]; } ttm_shape;
+
+typedef struct ttm_batched_plan ttm_batched_plan;
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char *ttm_status_string(int status);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int ttm_version(void);
+
+/*
+ * Supported (x_dtype, f_dtype, y_dtype, math) combinations of ttm_chain:
+ *   (F64,  F64, F64, F64)
+ *   (F32,  F32, F32, F32)   (F32, F32, F32, BF16)   (F32, F32, F32, BF16X3)
+ *   (BF16, F32, F32, F32)   (BF16, F32, F32, BF16)  (BF16, F32, F32, BF16X3)
+ * Anything else returns TTM_ERR_UNSUPPORTED.
+ */
+int ttm_chain_supported(int x_dtype, int f_dtype, int y_dtype, int math);
+
+/* Bytes of device workspace ttm_chain needs for this shape and arithmetic
+ * (0 for an invalid or unsupported request). */
+size_t ttm_chain_workspace_size(const ttm_shape *shape, int x_dtype, int math);
+
+/*
+ * Y = X x1 A x2 B x3 C (the chain written out above).
+ *
+ * shape     : sizes, every I[n] >= 1 and J[n] >= 1.
+ * X         : device, x_dtype, [I1][I2][I3], 16-byte aligned.
+ * A, B, C   : device, f_dtype, [J1][I1], [J2][I2], [J3][I3], 4-byte aligned.
+ * Y         : device, y_dtype, [J1][J2][J3], must not overlap any input or ws.
+ * ws        : device workspace of at least ttm_chain_workspace_size bytes,
+ *             16-byte aligned; its contents on entry are ignored.
+ * stream    : hipStream_t (opaque), NULL for the null stream.
+ *
+ * The contracted mode order inside the library is 3, then 2, then 1 (the
+ * contiguous mode first); mode products on distinct modes commute, so this is
+ * the same operator.  Results are deterministic: a repeated call with the same
+ * inputs gives bitwise-identical output.
+ */
+int ttm_chain(const ttm_shape *shape,
+              const void *X, int x_dtype,
+              const void *A, const void *B, const void *C, int f_dtype,
+              void *Y, int y_dtype, int math,
+              void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Gradient of a scalar loss L through the chain, given G = dL/dY:
+ *     dX = G x1 A^T x2 B^T x3 C^T
+ *     dA[j1,i1] = sum_{j2,j3} G[j1,j2,j3] (X x2 B x3 C)[i1,j2,j3]
+ *     dB[j2,i2] = sum_{j1,j3} G[j1,j2,j3] (X x1 A x3 C)[j1,i2,j3]
+ *     dC[j3,i3] = sum_{j1,j2} G[j1,j2,j3] (X x1 A x2 B)[j1,j2,i3]
+ * All tensors have one dtype, `dtype` (F64 or F32); math is F64 with F64 and
+ * F32 or BF16X3 with F32.  G is [J1][J2][J3]; dX, dA, dB, dC have the shapes
+ * of X, A, B, C and each may be NULL when not wanted (at least one must be
+ * given).  Outputs are overwritten (not accumulated) and must not overlap any
+ * input, each other, or ws.  Alignment and stream as for ttm_chain.
+ */
+size_t ttm_chain_backward_workspace_size(const ttm_shape *shape, int dtype, int math);
+int ttm_chain_backward(const ttm_shape *shape, const void *G,
+                       const void *X, const void *A, const void *B, const void *C, int dtype,
+                       void *dX, void *dA, void *dB, void *dC, int math,
+                       void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Batched chains over `count` independent cuboids (ragged sizes), run by one
+ * persistent kernel launch.
+ *
+ * dims_host : host array of count x 6 int64, per cuboid (I1,I2,I3,J1,J2,J3),
+ *             every entry in [1, 32].
+ * dtype     : F32 (math F32) or F64 (math F64).
+ * tune_cache: path of a JSON cache of autotuned launch shapes, or NULL.  When
+ *             the file holds an entry for this device and workload class it is
+ *             used; otherwise built-in defaults apply until ttm_batched_autotune.
+ * Buffers   : X, A, B, C, Y are the cuboids' tensors stored back to back in
+ *             cuboid order (each row-major as in ttm_chain); cuboid k starts at
+ *             the running sum of the element counts of cuboids 0..k-1.
+ *             ttm_batched_plan_totals reports the total element counts.
+ * Creating a plan allocates host memory and a small device metadata buffer
+ * and copies the metadata synchronously on `stream`; destroy frees both.
+ */
+int ttm_batched_plan_create(int64_t count, const int64_t *dims_host, int dtype, int math,
+                            const char *tune_cache, void *stream, ttm_batched_plan **out);
+int ttm_batched_plan_destroy(ttm_batched_plan *plan);
+
+/* totals[5] = elements of (X, A, B, C, Y) over all cuboids. */
+int ttm_batched_plan_totals(const ttm_batched_plan *plan, int64_t *totals);
+
+/* Y_k = X_k x1 A_k x2 B_k x3 C_k for every cuboid k, one launch on `stream`.
+ * Needs no workspace.  Y must not overlap the inputs. */
+int ttm_chain_batched(const ttm_batched_plan *plan, const void *X, const void *A,
+                      const void *B, const void *C, void *Y, void *stream);
+
+/*
+ * Same computation replayed from a HIP graph owned by the plan.  The graph
+ * holds the single persistent-kernel node; it is instantiated on first use and
+ * its node arguments are updated in place when the buffers change.  Not
+ * thread-safe for one plan (the graph is shared).
+ */
+int ttm_chain_batched_graph(ttm_batched_plan *plan, const void *X, const void *A,
+                            const void *B, const void *C, void *Y, void *stream);
+
+/*
+ * Reference launch pattern for comparison: one kernel launch per cuboid
+ * (count launches).  Same results as ttm_chain_batched.
+ */
+int ttm_chain_batched_loop(const ttm_batched_plan *plan, const void *X, const void *A,
+                           const void *B, const void *C, void *Y, void *stream);
+
+/*
+ * Autotune the batched launch shape: times every candidate (block size,
+ * resident blocks per compute unit) on the given buffers with HIP events,
+ * keeps the fastest in the plan, and, when the plan has a tune_cache path,
+ * rewrites that JSON file.  Synchronises `stream`.  Y is overwritten.
+ * best_out (nullable) receives the chosen candidate's mean time in ms.
+ */
+int ttm_batched_autotune(ttm_batched_plan *plan, const void *X, const void *A,
+                         const void *B, const void *C, void *Y, void *stream,
+                         int reps, double *best_ms_out);
+
+/* The plan's current launch shape: out[0] = threads per block, out[1] =
+ * blocks per compute unit, out[2] = total blocks. */
+int ttm_batched_plan_config(const ttm_batched_plan *plan, int *out);
+
+/*
+ * Per-kernel timing for measurement.  When enabled, every kernel the library
+ * launches is bracketed by HIP events recorded on the launch stream.
+ * ttm_timing_collect synchronises those events and returns, for up to `max`
+ * kernel names, the name (NUL-separated into names, each < 64 bytes), the
+ * number of launches and their summed duration in ms; it then clears the
+ * record.  Returns the number of entries written, or a negative status.
+ */
+int ttm_timing_enable(int on);
+int ttm_timing_collect(char *names, int64_t *counts, double *total_ms, int max);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TTM_H */

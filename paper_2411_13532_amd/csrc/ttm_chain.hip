@@ -1,0 +1,854 @@
+// ttm_chain.hip -- Y = X x1 A x2 B x3 C on one MI355X (gfx950).
+//
+// Three kernels per call:
+//   1. k_prep_factors : copy A, B, C into the workspace in the operand format
+//      of the chosen arithmetic (double, float, or bfloat16 hi/lo), with rows
+//      and columns zero-padded to the tile grid so no later load needs a guard.
+//   2. k_slab : one workgroup per (i1, i2-range).  It streams its rows of X
+//      once from HBM through an LDS double buffer and contracts mode 3 on the
+//      matrix cores, W = X[i1, rows, :] C^T.  The W tile never leaves the
+//      registers: its accumulator layout is reused directly as the k-major
+//      operand of the mode-2 contraction V[i1] += B[:, rows] W, which also
+//      stays in registers.  At the end the workgroup writes its partial
+//      V[i1] (J2 x J3, float) -- the only intermediate that reaches HBM
+//      (1/I3 of X's element count times J2*J3/I2, a few percent of X's bytes).
+//   3. k_mode1 : Y = A V_(1), summing the partials of V in a fixed order
+//      (no atomics, so every call is bitwise reproducible).
+#include <algorithm>
+#include <type_traits>
+
+#include "ttm_device.hpp"
+#include "ttm_host.hpp"
+
+namespace ttm {
+
+constexpr int SLAB_TM = 128;     // rows of X[i1] per tile
+constexpr int SLAB_THREADS = 256;
+
+struct PrepArgs {
+    const void *src[3];
+    void *hi[3];
+    void *lo[3];
+    int64_t J[3], I[3], Jpad[3], ld[3];
+};
+
+// Factor n of shape J x I (row-major, float or double) -> padded Jpad x ld
+// operand array(s).  For bfloat16 operands `hi` gets rne(v) and `lo` (when
+// non-null) gets rne(v - hi).
+template <typename ST, int MATH>
+__global__ void __launch_bounds__(256) k_prep_factors(PrepArgs a) {
+    const int f = blockIdx.y;
+    const int64_t n = a.Jpad[f] * a.ld[f];
+    const ST *src = static_cast<const ST *>(a.src[f]);
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t r = e / a.ld[f], c = e % a.ld[f];
+        const bool in = r < a.J[f] && c < a.I[f];
+        if constexpr (MATH == M_BF16 || MATH == M_BF16X3) {
+            const float v = in ? float(src[r * a.I[f] + c]) : 0.f;
+            uint32_t h, l;
+            bf16_split(v, h, l);
+            static_cast<uint16_t *>(a.hi[f])[e] = uint16_t(h);
+            if (a.lo[f]) static_cast<uint16_t *>(a.lo[f])[e] = uint16_t(l);
+        } else {
+            typedef typename MathTraits<MATH>::fac_t FT;
+            static_cast<FT *>(a.hi[f])[e] = in ? FT(src[r * a.I[f] + c]) : FT(0);
+        }
+    }
+}
+
+struct SlabArgs {
+    const void *X;
+    int64_t I1, I2, I3;
+    const void *Chi, *Clo;  // [J3pad][ldc]
+    int64_t ldc;
+    const void *Bhi, *Blo;  // [J2pad][ldb]
+    int64_t ldb;
+    void *V;                // [I1][P][J2pad][J3pad]
+    int64_t J2pad, J3pad;
+    int P, S;
+    int64_t rows_per_split;
+    int x_vec;              // 1: rows of X are 16-byte aligned and I3 is a multiple of the vector width
+};
+
+// ---------------------------------------------------------------------------
+// Loading one 16-byte LDS operand group (VE values of the operand type LT)
+// from X of storage type XT.  `raw` keeps what was fetched until it is
+// converted and stored after the current chunk's matrix-core work.
+// ---------------------------------------------------------------------------
+template <typename XT, typename LT> struct XGroup;
+
+template <typename T> struct XGroup<T, T> {          // same type: one 16-byte load
+    static constexpr int VE = 16 / sizeof(T);
+    V16 raw;
+    __device__ void fetch(const T *row, int64_t k, int64_t I3, bool valid, bool vec) {
+        if (!valid || k >= I3) { raw = zero16(); return; }
+        if (vec) { raw = ld16(row + k); return; }
+        T tmp[VE];
+#pragma unroll
+        for (int e = 0; e < VE; ++e) tmp[e] = (k + e < I3) ? row[k + e] : T(0);
+        raw = *reinterpret_cast<V16 *>(tmp);
+    }
+    __device__ void store(unsigned char *hi, unsigned char *) const { *reinterpret_cast<u32x4 *>(hi) = raw.u; }
+};
+
+template <> struct XGroup<uint16_t, float> {        // bf16 X, float operands: 8-byte load
+    static constexpr int VE = 4;
+    u32x2 raw;
+    __device__ void fetch(const uint16_t *row, int64_t k, int64_t I3, bool valid, bool vec) {
+        if (!valid || k >= I3) { raw = u32x2{0u, 0u}; return; }
+        if (vec) { raw = *reinterpret_cast<const u32x2 *>(row + k); return; }
+        uint32_t h[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) h[e] = (k + e < I3) ? row[k + e] : 0u;
+        raw = u32x2{pack2(h[0], h[1]), pack2(h[2], h[3])};
+    }
+    __device__ void store(unsigned char *hi, unsigned char *) const {
+        f32x4 v;
+        v[0] = __uint_as_float(raw[0] << 16);
+        v[1] = __uint_as_float(raw[0] & 0xffff0000u);
+        v[2] = __uint_as_float(raw[1] << 16);
+        v[3] = __uint_as_float(raw[1] & 0xffff0000u);
+        *reinterpret_cast<f32x4 *>(hi) = v;
+    }
+};
+
+template <> struct XGroup<float, uint16_t> {        // float X, bf16 operands: 32-byte load, split on store
+    static constexpr int VE = 8;
+    V16 raw0, raw1;
+    __device__ void fetch(const float *row, int64_t k, int64_t I3, bool valid, bool vec) {
+        if (!valid || k >= I3) { raw0 = zero16(); raw1 = zero16(); return; }
+        if (vec) { raw0 = ld16(row + k); raw1 = ld16(row + k + 4); return; }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            raw0.f[e] = (k + e < I3) ? row[k + e] : 0.f;
+            raw1.f[e] = (k + 4 + e < I3) ? row[k + 4 + e] : 0.f;
+        }
+    }
+    __device__ void store(unsigned char *hi, unsigned char *lo) const {
+        uint32_t h[8], l[8];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            bf16_split(raw0.f[e], h[e], l[e]);
+            bf16_split(raw1.f[e], h[4 + e], l[4 + e]);
+        }
+        *reinterpret_cast<u32x4 *>(hi) = u32x4{pack2(h[0], h[1]), pack2(h[2], h[3]), pack2(h[4], h[5]), pack2(h[6], h[7])};
+        if (lo) *reinterpret_cast<u32x4 *>(lo) = u32x4{pack2(l[0], l[1]), pack2(l[2], l[3]), pack2(l[4], l[5]), pack2(l[6], l[7])};
+    }
+};
+
+template <int MATH, typename XT> struct SlabCfg {
+    typedef MathTraits<MATH> TR;
+    typedef typename TR::lds_t LT;
+    static constexpr int VE = TR::VE;
+    static constexpr int KG = TR::KG;             // k per k-group (64 bytes of LT per row)
+    static constexpr int KC = 2 * KG;             // k per chunk (128 bytes of LT per row)
+    static constexpr int ROWB = KC * int(sizeof(LT)) + 16;   // padded LDS row stride
+    static constexpr int TILEB = SLAB_TM * ROWB;
+    static constexpr bool XLO = (MATH == M_BF16X3) && std::is_same<XT, float>::value;
+    static constexpr int GROUPS = SLAB_TM * 8 / SLAB_THREADS;  // 16-byte LDS groups per thread per chunk
+    static constexpr size_t lds_bytes() { return size_t(TILEB) * 2 * (XLO ? 2 : 1); }
+};
+
+// Mode-2 step: V[jb][nb] += B[j2 rows, tile rows] * W[tile rows, cols].
+// f32/f64: per 16-row block, the accumulator register r of lane (g, c) is
+// W[acc_row(g, r)][c], so MFMA r takes k-slot g <-> row acc_row(g, r).
+template <int MATH, int MB, int NBW, int JB>
+__device__ __forceinline__ void slab_mode2(typename MathTraits<MATH>::accv_t (&vacc)[JB][NBW],
+                                           const typename MathTraits<MATH>::accv_t (&wacc)[MB][NBW],
+                                           const SlabArgs &a, int jbase, int64_t wrow0, int l16, int g) {
+    if constexpr (MATH == M_F32 || MATH == M_F64) {
+        typedef typename MathTraits<MATH>::fac_t FT;
+        const FT *Bp = static_cast<const FT *>(a.Bhi);
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+#pragma unroll
+            for (int jb = 0; jb < JB; ++jb) {
+                {
+                    const FT *brow = Bp + int64_t((jbase + jb) * 16 + l16) * a.ldb + wrow0 + mb * 16;
+                    FT bv[4];
+                    if constexpr (MATH == M_F32) {
+                        V16 t = ld16(brow + 4 * g);        // rows 4g .. 4g+3
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) bv[r] = t.f[r];
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) bv[r] = brow[MathTraits<MATH>::acc_row(g, r)];
+                    }
+#pragma unroll
+                    for (int nb = 0; nb < NBW; ++nb)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            if constexpr (MATH == M_F32) vacc[jb][nb] = mfma_f32(bv[r], wacc[mb][nb][r], vacc[jb][nb]);
+                            else vacc[jb][nb] = mfma_f64(bv[r], wacc[mb][nb][r], vacc[jb][nb]);
+                        }
+                }
+            }
+            // keep the next block's loads from being hoisted (register pressure)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    } else {
+        // bf16: two stacked 16-row blocks give a lane the 8 values
+        // {W[32p + 4g + e], W[32p + 16 + 4g + e]}, e = 0..3 -> one k-slot group.
+        const uint16_t *Bh = static_cast<const uint16_t *>(a.Bhi);
+        const uint16_t *Bl = static_cast<const uint16_t *>(a.Blo);
+#pragma unroll
+        for (int p = 0; p < MB / 2; ++p) {
+            u32x4 wh[NBW], wl[NBW];
+#pragma unroll
+            for (int nb = 0; nb < NBW; ++nb) {
+                uint32_t h[8], l[8];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    if constexpr (MATH == M_BF16X3) {
+                        bf16_split(wacc[2 * p][nb][e], h[e], l[e]);
+                        bf16_split(wacc[2 * p + 1][nb][e], h[4 + e], l[4 + e]);
+                    } else {
+                        h[e] = bf16_rne_bits(wacc[2 * p][nb][e]);
+                        h[4 + e] = bf16_rne_bits(wacc[2 * p + 1][nb][e]);
+                        l[e] = l[4 + e] = 0;
+                    }
+                }
+                wh[nb] = u32x4{pack2(h[0], h[1]), pack2(h[2], h[3]), pack2(h[4], h[5]), pack2(h[6], h[7])};
+                wl[nb] = u32x4{pack2(l[0], l[1]), pack2(l[2], l[3]), pack2(l[4], l[5]), pack2(l[6], l[7])};
+            }
+#pragma unroll
+            for (int jb = 0; jb < JB; ++jb) {
+                {
+                    const int64_t off = int64_t((jbase + jb) * 16 + l16) * a.ldb + wrow0 + 32 * p + 4 * g;
+                    const u32x2 h0 = *reinterpret_cast<const u32x2 *>(Bh + off);
+                    const u32x2 h1 = *reinterpret_cast<const u32x2 *>(Bh + off + 16);
+                    const u32x4 bh = u32x4{h0[0], h0[1], h1[0], h1[1]};
+                    if constexpr (MATH == M_BF16X3) {
+                        const u32x2 l0 = *reinterpret_cast<const u32x2 *>(Bl + off);
+                        const u32x2 l1 = *reinterpret_cast<const u32x2 *>(Bl + off + 16);
+                        const u32x4 bl = u32x4{l0[0], l0[1], l1[0], l1[1]};
+#pragma unroll
+                        for (int nb = 0; nb < NBW; ++nb) {
+                            vacc[jb][nb] = mfma_bf16(bh, wh[nb], vacc[jb][nb]);
+                            vacc[jb][nb] = mfma_bf16(bh, wl[nb], vacc[jb][nb]);
+                            vacc[jb][nb] = mfma_bf16(bl, wh[nb], vacc[jb][nb]);
+                        }
+                    } else {
+#pragma unroll
+                        for (int nb = 0; nb < NBW; ++nb) vacc[jb][nb] = mfma_bf16(bh, wh[nb], vacc[jb][nb]);
+                    }
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+// One workgroup: 4 waves arranged WR x WC over (tile rows) x (columns j3).
+// Wave (wr, wc) owns RW = 128 / WR rows of every 128-row tile and NBW 16-wide
+// column blocks.  The workgroup covers columns blockIdx.y * (WC*NBW*16) ...
+// and j2 blocks blockIdx.z * JBMAX ...; its partial index of V is s*WR + wr.
+template <int MATH, typename XT, int WC, int NBW, int JB>
+__global__ void __launch_bounds__(SLAB_THREADS, 2) k_slab(const SlabArgs a) {
+    typedef SlabCfg<MATH, XT> CF;
+    typedef typename CF::LT LT;
+    typedef typename MathTraits<MATH>::accv_t accv_t;
+    typedef typename MathTraits<MATH>::acc_t acc_t;
+    typedef typename MathTraits<MATH>::fac_t FT;
+    constexpr int WR = 4 / WC, RW = SLAB_TM / WR, MB = RW / 16;
+    constexpr int KG = CF::KG, KC = CF::KC, VE = CF::VE;
+    constexpr int GROUPS = CF::GROUPS;
+    static_assert(MB >= 2 && MB % 2 == 0, "row blocks per wave");
+
+    extern __shared__ __align__(16) unsigned char smem[];
+    unsigned char *tile_hi = smem;
+    unsigned char *tile_lo = smem + 2 * CF::TILEB;   // used only when CF::XLO
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave / WC, wc = wave % WC;
+    const int l16 = lane & 15, g = lane >> 4;
+
+    const int64_t i1 = blockIdx.x / a.S;
+    const int s = int(blockIdx.x % a.S);
+    const int64_t row_begin = int64_t(s) * a.rows_per_split;
+    const int64_t row_end = a.I2 < row_begin + a.rows_per_split ? a.I2 : row_begin + a.rows_per_split;
+    const int64_t nrows = row_end > row_begin ? row_end - row_begin : 0;
+    const int64_t col0 = int64_t(blockIdx.y) * (WC * NBW * 16) + wc * NBW * 16;
+    const int jbase = int(blockIdx.z) * JB;
+
+    const XT *Xs = static_cast<const XT *>(a.X) + i1 * a.I2 * a.I3;
+    const int64_t nk = ceil_div(a.I3, KC);
+    const int64_t ntiles = ceil_div(nrows, SLAB_TM);
+    const int64_t nq = ntiles * nk;
+    const bool vec = a.x_vec != 0;
+
+    accv_t vacc[JB][NBW];
+    accv_t wacc[MB][NBW];
+#pragma unroll
+    for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+        for (int nb = 0; nb < NBW; ++nb) vacc[jb][nb] = zero_accv<accv_t>();
+
+    XGroup<XT, LT> pre[GROUPS];
+    auto fetch = [&](int64_t q) {
+        const int64_t t = q / nk, kc = q % nk;
+        const int64_t r0 = row_begin + t * SLAB_TM;
+#pragma unroll
+        for (int j = 0; j < GROUPS; ++j) {
+            const int gi = tid + SLAB_THREADS * j;
+            const int r = gi >> 3, cg = gi & 7;
+            const int64_t grow = r0 + r;
+            pre[j].fetch(Xs + grow * a.I3, kc * KC + cg * VE, a.I3, grow < row_end, vec);
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int j = 0; j < GROUPS; ++j) {
+            const int gi = tid + SLAB_THREADS * j;
+            const int r = gi >> 3, cg = gi & 7;
+            const int off = buf * CF::TILEB + r * CF::ROWB + cg * 16;
+            pre[j].store(tile_hi + off, CF::XLO ? tile_lo + off : nullptr);
+        }
+    };
+
+    const FT *Ch = static_cast<const FT *>(a.Chi);
+    const FT *Cl = static_cast<const FT *>(a.Clo);
+
+    if (nq > 0) {
+        fetch(0);
+        store(0);
+    }
+    __syncthreads();
+
+    int64_t q = 0;
+    for (int64_t t = 0; t < ntiles; ++t) {
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < NBW; ++nb) wacc[mb][nb] = zero_accv<accv_t>();
+
+        for (int64_t kc = 0; kc < nk; ++kc, ++q) {
+            if (q + 1 < nq) fetch(q + 1);
+
+            const int buf = int(q & 1);
+#pragma unroll
+            for (int kg = 0; kg < 2; ++kg) {
+                const int64_t k0 = kc * KC + kg * KG + g * VE;
+                V16 bh[NBW], bl[NBW];
+#pragma unroll
+                for (int nb = 0; nb < NBW; ++nb) {
+                    const int64_t off = (col0 + nb * 16 + l16) * a.ldc + k0;
+                    bh[nb] = ld16(Ch + off);
+                    if constexpr (MATH == M_BF16X3) bl[nb] = ld16(Cl + off);
+                }
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb) {
+                    const int loff = buf * CF::TILEB + (wr * RW + mb * 16 + l16) * CF::ROWB + kg * 64 + g * 16;
+                    V16 ah;
+                    ah.u = *reinterpret_cast<const u32x4 *>(tile_hi + loff);
+#pragma unroll
+                    for (int nb = 0; nb < NBW; ++nb) {
+                        mma_kgroup<MATH == M_BF16X3 ? M_BF16 : MATH>(wacc[mb][nb], ah, bh[nb]);
+                        if constexpr (MATH == M_BF16X3) mma_kgroup<M_BF16>(wacc[mb][nb], ah, bl[nb]);
+                    }
+                    if constexpr (CF::XLO) {
+                        V16 al;
+                        al.u = *reinterpret_cast<const u32x4 *>(tile_lo + loff);
+#pragma unroll
+                        for (int nb = 0; nb < NBW; ++nb) mma_kgroup<M_BF16>(wacc[mb][nb], al, bh[nb]);
+                    }
+                }
+            }
+            if (q + 1 < nq) store(buf ^ 1);
+            __syncthreads();
+        }
+        const int64_t wrow0 = row_begin + t * SLAB_TM + wr * RW;
+        slab_mode2<MATH, MB, NBW, JB>(vacc, wacc, a, jbase, wrow0, l16, g);
+    }
+
+    // Partial V[i1][s*WR + wr][j2][j3]: lane (g, c) register r holds
+    // row j2 = 16*jb + acc_row(g, r), column j3 = col0 + 16*nb + c.
+    acc_t *V = static_cast<acc_t *>(a.V);
+    const int64_t part = int64_t(s) * WR + wr;
+    acc_t *Vp = V + (i1 * a.P + part) * a.J2pad * a.J3pad;
+#pragma unroll
+    for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+        for (int nb = 0; nb < NBW; ++nb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t j2 = int64_t(jbase + jb) * 16 + MathTraits<MATH>::acc_row(g, r);
+                Vp[j2 * a.J3pad + col0 + nb * 16 + l16] = vacc[jb][nb][r];
+            }
+}
+
+// ---------------------------------------------------------------------------
+// Mode-1 contraction with partial sums:
+//   Y[j1, n] = sum_i1 A[j1, i1] * sum_p V[i1][p][n],   n = j2 * J3pad + j3.
+// A workgroup owns 64 columns n (wave w: columns 16w..16w+15) and every j1
+// row (MBK 16-row blocks); grid.y splits the i1 range.  V is streamed once:
+// each lane reads one column over VE consecutive rows (a wave reads 256
+// contiguous bytes per row), converts to the operand format and stores the
+// VE values as one 16-byte LDS word, k-contiguous, which is exactly the
+// k-slot fragment the B operand wants.  With one split the result goes to Y;
+// otherwise to per-split partials summed by k_mode1_reduce.
+// ---------------------------------------------------------------------------
+struct Mode1Args {
+    const void *Ahi, *Alo;   // [J1pad][lda]
+    int64_t lda;
+    const void *V;           // [I1][P][NN]
+    int64_t I1;
+    int P;
+    int64_t NN, J3pad;
+    void *Y;                 // final output, used when KS == 1
+    void *Ypart;             // [KS][J1pad][NN] partials, used when KS > 1
+    int64_t J1, J2, J3, J1pad;
+    int KS;
+    int64_t rows_per_split;
+};
+
+template <int MATH>
+struct Mode1Cfg {
+    typedef MathTraits<MATH> TR;
+    typedef typename TR::lds_t LT;
+    static constexpr int VE = TR::VE, KG = TR::KG;
+    static constexpr int KT = 2 * KG;                                  // rows per chunk
+    static constexpr int ROWB = KT * int(sizeof(LT)) + 16;             // LDS stride per column
+    static constexpr int BUFB = 64 * ROWB;
+    static constexpr int ITEMS = KT * 64 / (256 * VE);                 // 16-byte words per thread per chunk
+    static constexpr bool SPLIT = (MATH == M_BF16X3);
+};
+
+template <int MATH, int MBK>
+__global__ void __launch_bounds__(256) k_mode1(const Mode1Args a) {
+    typedef Mode1Cfg<MATH> CF;
+    typedef MathTraits<MATH> TR;
+    typedef typename TR::accv_t accv_t;
+    typedef typename TR::acc_t acc_t;
+    typedef typename TR::fac_t FT;
+    constexpr int VE = CF::VE, KG = CF::KG, KT = CF::KT, ITEMS = CF::ITEMS;
+    __shared__ __align__(16) unsigned char lds[2 * CF::BUFB * (CF::SPLIT ? 2 : 1)];
+    unsigned char *lhi = lds, *llo = lds + 2 * CF::BUFB;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int l16 = lane & 15, g = lane >> 4;
+    const int64_t n0 = int64_t(blockIdx.x) * 64;
+    const int ks = int(blockIdx.y);
+    const int64_t kb = int64_t(ks) * a.rows_per_split;
+    const int64_t ke = a.I1 < kb + a.rows_per_split ? a.I1 : kb + a.rows_per_split;
+    const int64_t nch = ke > kb ? ceil_div(ke - kb, KT) : 0;
+    const acc_t *V = static_cast<const acc_t *>(a.V);
+    const FT *Ah = static_cast<const FT *>(a.Ahi);
+    const FT *Al = static_cast<const FT *>(a.Alo);
+
+    // loader: thread (column c = tid % 64, word w = tid / 64 + 4*item) covers rows VE*w .. VE*w+VE-1
+    const int lc = tid & 63, lw = tid >> 6;
+    acc_t pre[ITEMS][VE];
+    auto fetch = [&](int64_t ch) {
+        const int64_t r0 = kb + ch * KT;
+#pragma unroll
+        for (int it = 0; it < ITEMS; ++it)
+#pragma unroll
+            for (int e = 0; e < VE; ++e) {
+                const int64_t k = r0 + (lw + 4 * it) * VE + e;
+                acc_t s = acc_t(0);
+                if (k < ke) {
+                    const acc_t *vp = V + k * a.P * a.NN + n0 + lc;
+                    for (int p = 0; p < a.P; ++p) s += vp[int64_t(p) * a.NN];
+                }
+                pre[it][e] = s;
+            }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int it = 0; it < ITEMS; ++it) {
+            const int off = buf * CF::BUFB + lc * CF::ROWB + (lw + 4 * it) * 16;
+            if constexpr (MATH == M_F32) {
+                *reinterpret_cast<f32x4 *>(lhi + off) = f32x4{pre[it][0], pre[it][1], pre[it][2], pre[it][3]};
+            } else if constexpr (MATH == M_F64) {
+                *reinterpret_cast<f64x2 *>(lhi + off) = f64x2{pre[it][0], pre[it][1]};
+            } else {
+                uint32_t h[8], l[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    if constexpr (MATH == M_BF16X3) bf16_split(pre[it][e], h[e], l[e]);
+                    else { h[e] = bf16_rne_bits(pre[it][e]); l[e] = 0; }
+                }
+                *reinterpret_cast<u32x4 *>(lhi + off) =
+                    u32x4{pack2(h[0], h[1]), pack2(h[2], h[3]), pack2(h[4], h[5]), pack2(h[6], h[7])};
+                if constexpr (CF::SPLIT)
+                    *reinterpret_cast<u32x4 *>(llo + off) =
+                        u32x4{pack2(l[0], l[1]), pack2(l[2], l[3]), pack2(l[4], l[5]), pack2(l[6], l[7])};
+            }
+        }
+    };
+
+    accv_t acc[MBK];
+#pragma unroll
+    for (int mb = 0; mb < MBK; ++mb) acc[mb] = zero_accv<accv_t>();
+
+    if (nch > 0) {
+        fetch(0);
+        store(0);
+    }
+    __syncthreads();
+    for (int64_t ch = 0; ch < nch; ++ch) {
+        if (ch + 1 < nch) fetch(ch + 1);
+        const int buf = int(ch & 1);
+#pragma unroll
+        for (int kg = 0; kg < 2; ++kg) {
+            const int loff = buf * CF::BUFB + (wave * 16 + l16) * CF::ROWB + kg * 64 + g * 16;
+            V16 bh, bl;
+            bh.u = *reinterpret_cast<const u32x4 *>(lhi + loff);
+            if constexpr (CF::SPLIT) bl.u = *reinterpret_cast<const u32x4 *>(llo + loff);
+            const int64_t k0 = kb + ch * KT + kg * KG + g * VE;
+#pragma unroll
+            for (int mb = 0; mb < MBK; ++mb) {
+                const int64_t off = (int64_t(blockIdx.z) * MBK * 16 + mb * 16 + l16) * a.lda + k0;
+                const V16 ah = ld16(Ah + off);
+                mma_kgroup<MATH == M_BF16X3 ? M_BF16 : MATH>(acc[mb], ah, bh);
+                if constexpr (CF::SPLIT) {
+                    const V16 al = ld16(Al + off);
+                    mma_kgroup<M_BF16>(acc[mb], ah, bl);
+                    mma_kgroup<M_BF16>(acc[mb], al, bh);
+                }
+            }
+        }
+        if (ch + 1 < nch) store(buf ^ 1);
+        __syncthreads();
+    }
+
+    const int64_t n = n0 + wave * 16 + l16;
+    const int64_t m0 = int64_t(blockIdx.z) * MBK * 16;
+    if (a.KS == 1) {
+        const int64_t j2 = n / a.J3pad, j3 = n % a.J3pad;
+        if (j2 >= a.J2 || j3 >= a.J3) return;
+        acc_t *Y = static_cast<acc_t *>(a.Y);
+#pragma unroll
+        for (int mb = 0; mb < MBK; ++mb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t j1 = m0 + mb * 16 + TR::acc_row(g, r);
+                if (j1 < a.J1) Y[(j1 * a.J2 + j2) * a.J3 + j3] = acc[mb][r];
+            }
+    } else {
+        acc_t *Yp = static_cast<acc_t *>(a.Ypart) + int64_t(ks) * a.J1pad * a.NN;
+#pragma unroll
+        for (int mb = 0; mb < MBK; ++mb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t j1 = m0 + mb * 16 + TR::acc_row(g, r);
+                Yp[j1 * a.NN + n] = acc[mb][r];
+            }
+    }
+}
+
+// Y[j1][j2][j3] = sum_ks Ypart[ks][j1][j2 * J3pad + j3] in increasing ks order.
+template <typename T>
+__global__ void __launch_bounds__(256) k_mode1_reduce(const Mode1Args a) {
+    const int64_t total = a.J1 * a.J2 * a.J3;
+    const T *Yp = static_cast<const T *>(a.Ypart);
+    T *Y = static_cast<T *>(a.Y);
+    for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < total; e += int64_t(gridDim.x) * 256) {
+        const int64_t j3 = e % a.J3, j2 = (e / a.J3) % a.J2, j1 = e / (a.J2 * a.J3);
+        const T *p = Yp + j1 * a.NN + j2 * a.J3pad + j3;
+        T s = T(0);
+        for (int k = 0; k < a.KS; ++k) s += p[int64_t(k) * a.J1pad * a.NN];
+        Y[e] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host planning
+// ---------------------------------------------------------------------------
+struct ChainPlan {
+    int math, xdt;
+    int WC, NBW, WR, JBMAX, JB, MBK;
+    int64_t cols;                 // j3 columns per workgroup
+    int64_t J3pad, J2pad, J1pad;
+    int64_t n_j3_tiles, n_j2_tiles, n_m1_tiles;
+    int KS;                       // i1 splits of the mode-1 kernel
+    int64_t m1_rows_per_split;
+    int S, P;
+    int64_t rows_per_split;
+    int64_t ldc, ldb, lda;
+    size_t fsz;                   // bytes per factor operand element
+    size_t acc_sz;
+    size_t off_Chi, off_Clo, off_Bhi, off_Blo, off_Ahi, off_Alo, off_V, off_Yp, total;
+    bool split;                   // factors need hi/lo
+};
+
+static inline size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+static bool combo_ok(int x, int f, int y, int m) {
+    if (m == TTM_MATH_F64) return x == TTM_F64 && f == TTM_F64 && y == TTM_F64;
+    if (f != TTM_F32 || y != TTM_F32) return false;
+    if (m == TTM_MATH_F32 || m == TTM_MATH_BF16 || m == TTM_MATH_BF16X3) return x == TTM_F32 || x == TTM_BF16;
+    return false;
+}
+
+static bool make_plan(const ttm_shape &s, int xdt, int math, ChainPlan &p) {
+    p = ChainPlan();
+    p.math = math;
+    p.xdt = xdt;
+    const int64_t I1 = s.I[0], I2 = s.I[1], I3 = s.I[2];
+    const int64_t J1 = s.J[0], J2 = s.J[1], J3 = s.J[2];
+    const bool bf = (math == TTM_MATH_BF16 || math == TTM_MATH_BF16X3);
+    const int KG = math == TTM_MATH_F64 ? 8 : (math == TTM_MATH_F32 ? 16 : 32);
+    const int KC = 2 * KG;
+    p.split = (math == TTM_MATH_BF16X3);
+    p.fsz = math == TTM_MATH_F64 ? 8 : (bf ? 2 : 4);
+    p.acc_sz = math == TTM_MATH_F64 ? 8 : 4;
+
+    // columns (j3) per workgroup and how the 4 waves share them
+    const int64_t J3r = round_up(J3, 16);
+    if (J3r <= 16) { p.WC = 1; p.NBW = 1; }
+    else if (J3r <= 32) { p.WC = 2; p.NBW = 1; }
+    else if (J3r <= 64 || math == TTM_MATH_F64) { p.WC = 4; p.NBW = 1; }
+    else { p.WC = 4; p.NBW = 2; }
+    p.WR = 4 / p.WC;
+    p.cols = int64_t(p.WC) * p.NBW * 16;
+    p.n_j3_tiles = ceil_div(J3r, p.cols);
+    p.J3pad = p.n_j3_tiles * p.cols;
+    p.JBMAX = math == TTM_MATH_F64 ? 4 : 8;
+    {
+        const int64_t jbn = ceil_div(J2, 16);
+        p.JB = jbn >= p.JBMAX ? p.JBMAX : (jbn > 2 ? 4 : (jbn > 1 ? 2 : 1));
+    }
+    p.n_j2_tiles = ceil_div(ceil_div(J2, 16), p.JB);
+    p.J2pad = p.n_j2_tiles * p.JB * 16;
+
+    // split the i2 rows of a slab so the grid has enough workgroups
+    const int64_t base = I1 * p.n_j3_tiles * p.n_j2_tiles;
+    const int64_t max_s = ceil_div(I2, SLAB_TM);
+    int64_t S = ceil_div(1024, base);
+    if (S < 1) S = 1;
+    if (S > max_s) S = max_s;
+    if (S > 64) S = 64;
+    p.rows_per_split = round_up(ceil_div(I2, S), SLAB_TM);
+    p.S = int(ceil_div(I2, p.rows_per_split));
+    p.P = p.S * p.WR;
+
+    // mode-1 kernel tiling
+    const int64_t J1b = ceil_div(J1, 16);
+    const int mbk_max = math == TTM_MATH_F64 ? 4 : 8;
+    p.MBK = J1b >= mbk_max ? mbk_max : (J1b > 2 ? 4 : (J1b > 1 ? 2 : 1));
+    p.n_m1_tiles = ceil_div(J1b, p.MBK);
+    p.J1pad = p.n_m1_tiles * p.MBK * 16;
+
+    p.ldc = round_up(I3, KC);
+    p.ldb = round_up(I2, SLAB_TM);
+    p.lda = round_up(I1, KC);
+
+    // mode-1 kernel: split the i1 range while the column tiles alone leave the
+    // GPU short of workgroups, keeping the partials at most half of V's size
+    {
+        const int64_t NN = p.J2pad * p.J3pad;
+        const int64_t wg = (NN / 64) * p.n_m1_tiles;
+        int64_t ks = ceil_div(1024, wg);
+        const int64_t ks_bytes = (I1 * p.P) / (2 * p.J1pad);
+        if (ks > ks_bytes) ks = ks_bytes;
+        if (ks > ceil_div(I1, KC)) ks = ceil_div(I1, KC);
+        if (ks > 64) ks = 64;
+        if (ks < 1) ks = 1;
+        p.m1_rows_per_split = round_up(ceil_div(I1, ks), KC);
+        p.KS = int(ceil_div(I1, p.m1_rows_per_split));
+    }
+
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = al256(off + bytes); return o; };
+    p.off_Chi = take(size_t(p.J3pad) * p.ldc * p.fsz);
+    p.off_Clo = p.split ? take(size_t(p.J3pad) * p.ldc * p.fsz) : 0;
+    p.off_Bhi = take(size_t(p.J2pad) * p.ldb * p.fsz);
+    p.off_Blo = p.split ? take(size_t(p.J2pad) * p.ldb * p.fsz) : 0;
+    p.off_Ahi = take(size_t(p.J1pad) * p.lda * p.fsz);
+    p.off_Alo = p.split ? take(size_t(p.J1pad) * p.lda * p.fsz) : 0;
+    p.off_V = take(size_t(I1) * p.P * p.J2pad * p.J3pad * p.acc_sz);
+    p.off_Yp = p.KS > 1 ? take(size_t(p.KS) * p.J1pad * p.J2pad * p.J3pad * p.acc_sz) : 0;
+    p.total = off;
+    // launch-grid limits
+    if (I1 * p.S > 0x7fffffffLL || p.n_j3_tiles > 65535 || p.n_j2_tiles > 65535 || p.n_m1_tiles > 65535 ||
+        p.J2pad * p.J3pad / 64 > 0x7fffffffLL || p.KS > 65535)
+        return false;
+    return true;
+}
+
+template <int MATH, typename XT, int WC, int NBW, int JB>
+static int launch_slab(const ChainPlan &p, const SlabArgs &a, hipStream_t st) {
+    typedef SlabCfg<MATH, XT> CF;
+    dim3 grid(unsigned(a.I1 * a.S), unsigned(p.n_j3_tiles), unsigned(p.n_j2_tiles));
+    const size_t lds = CF::lds_bytes();
+    static bool attr_set = false;
+    if (!attr_set) {
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_slab<MATH, XT, WC, NBW, JB>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)) != hipSuccess)
+            return TTM_ERR_HIP;
+        attr_set = true;
+    }
+    return launch("ttm_slab", st, [&] {
+        hipLaunchKernelGGL((k_slab<MATH, XT, WC, NBW, JB>), grid, dim3(SLAB_THREADS), lds, st, a);
+    });
+}
+
+template <int MATH, typename XT, int WC, int NBW>
+static int dispatch_slab_jb(const ChainPlan &p, const SlabArgs &a, hipStream_t st) {
+    switch (p.JB) {
+        case 1: return launch_slab<MATH, XT, WC, NBW, 1>(p, a, st);
+        case 2: return launch_slab<MATH, XT, WC, NBW, 2>(p, a, st);
+        case 4: return launch_slab<MATH, XT, WC, NBW, 4>(p, a, st);
+        default:
+            if constexpr (MATH != M_F64) return launch_slab<MATH, XT, WC, NBW, 8>(p, a, st);
+            return TTM_ERR_UNSUPPORTED;
+    }
+}
+
+template <int MATH, typename XT>
+static int dispatch_slab(const ChainPlan &p, const SlabArgs &a, hipStream_t st) {
+    if (p.WC == 1) return dispatch_slab_jb<MATH, XT, 1, 1>(p, a, st);
+    if (p.WC == 2) return dispatch_slab_jb<MATH, XT, 2, 1>(p, a, st);
+    if (p.NBW == 1) return dispatch_slab_jb<MATH, XT, 4, 1>(p, a, st);
+    if constexpr (MATH != M_F64) return dispatch_slab_jb<MATH, XT, 4, 2>(p, a, st);
+    return TTM_ERR_UNSUPPORTED;
+}
+
+template <int MATH>
+static int dispatch_mode1(const ChainPlan &p, const Mode1Args &a, hipStream_t st) {
+    typedef typename MathTraits<MATH>::acc_t acc_t;
+    dim3 grid(unsigned(p.J2pad * p.J3pad / 64), unsigned(p.KS), unsigned(p.n_m1_tiles));
+    auto go = [&](auto kern) {
+        return launch("ttm_mode1", st, [&] { hipLaunchKernelGGL(kern, grid, dim3(256), 0, st, a); });
+    };
+    int rc;
+    switch (p.MBK) {
+        case 1: rc = go(k_mode1<MATH, 1>); break;
+        case 2: rc = go(k_mode1<MATH, 2>); break;
+        case 4: rc = go(k_mode1<MATH, 4>); break;
+        default:
+            if constexpr (MATH != M_F64) rc = go(k_mode1<MATH, 8>);
+            else rc = TTM_ERR_UNSUPPORTED;
+    }
+    if (rc || p.KS == 1) return rc;
+    const int64_t total = a.J1 * a.J2 * a.J3;
+    dim3 rgrid(unsigned(std::min<int64_t>(ceil_div(total, 256), 8192)));
+    return launch("ttm_mode1_reduce", st, [&] { hipLaunchKernelGGL((k_mode1_reduce<acc_t>), rgrid, dim3(256), 0, st, a); });
+}
+
+template <int MATH>
+static int run_chain(const ChainPlan &p, const ttm_shape &s, const void *X, const void *A, const void *B,
+                     const void *C, void *Y, unsigned char *ws, hipStream_t st) {
+    // 1. factor operands
+    PrepArgs pa;
+    const void *src[3] = {A, B, C};
+    const size_t offh[3] = {p.off_Ahi, p.off_Bhi, p.off_Chi}, offl[3] = {p.off_Alo, p.off_Blo, p.off_Clo};
+    const int64_t Jpad[3] = {p.J1pad, p.J2pad, p.J3pad}, ld[3] = {p.lda, p.ldb, p.ldc};
+    int64_t maxn = 0;
+    for (int f = 0; f < 3; ++f) {
+        pa.src[f] = src[f];
+        pa.hi[f] = ws + offh[f];
+        pa.lo[f] = p.split ? ws + offl[f] : nullptr;
+        pa.J[f] = s.J[f];
+        pa.I[f] = s.I[f];
+        pa.Jpad[f] = Jpad[f];
+        pa.ld[f] = ld[f];
+        maxn = std::max<int64_t>(maxn, Jpad[f] * ld[f]);
+    }
+    dim3 pgrid(unsigned(std::min<int64_t>(ceil_div(maxn, 256), 4096)), 3);
+    int rc;
+    if constexpr (MATH == M_F64)
+        rc = launch("ttm_prep", st, [&] { hipLaunchKernelGGL((k_prep_factors<double, MATH>), pgrid, dim3(256), 0, st, pa); });
+    else
+        rc = launch("ttm_prep", st, [&] { hipLaunchKernelGGL((k_prep_factors<float, MATH>), pgrid, dim3(256), 0, st, pa); });
+    if (rc) return rc;
+
+    // 2. slab kernel (modes 3 and 2)
+    SlabArgs sa;
+    sa.X = X;
+    sa.I1 = s.I[0]; sa.I2 = s.I[1]; sa.I3 = s.I[2];
+    sa.Chi = ws + p.off_Chi; sa.Clo = p.split ? ws + p.off_Clo : nullptr; sa.ldc = p.ldc;
+    sa.Bhi = ws + p.off_Bhi; sa.Blo = p.split ? ws + p.off_Blo : nullptr; sa.ldb = p.ldb;
+    sa.V = ws + p.off_V;
+    sa.J2pad = p.J2pad; sa.J3pad = p.J3pad;
+    sa.P = p.P; sa.S = p.S;
+    sa.rows_per_split = p.rows_per_split;
+    const size_t xsz = dtype_size(p.xdt);
+    sa.x_vec = ((s.I[2] * int64_t(xsz)) % 16 == 0) && aligned(X, 16);
+    if constexpr (MATH == M_F64) {
+        rc = dispatch_slab<M_F64, double>(p, sa, st);
+    } else if (p.xdt == TTM_BF16) {
+        // bf16 X: 8-byte groups for float operands need 8-byte rows
+        if constexpr (MATH == M_F32) sa.x_vec = ((s.I[2] * 2) % 8 == 0) && aligned(X, 16);
+        rc = dispatch_slab<MATH, uint16_t>(p, sa, st);
+    } else {
+        if constexpr (MATH == M_BF16 || MATH == M_BF16X3) sa.x_vec = ((s.I[2] * 4) % 32 == 0) && aligned(X, 16);
+        rc = dispatch_slab<MATH, float>(p, sa, st);
+    }
+    if (rc) return rc;
+
+    // 3. mode 1
+    Mode1Args ma;
+    ma.Ahi = ws + p.off_Ahi; ma.Alo = p.split ? ws + p.off_Alo : nullptr; ma.lda = p.lda;
+    ma.V = ws + p.off_V; ma.I1 = s.I[0]; ma.P = p.P;
+    ma.NN = p.J2pad * p.J3pad; ma.J3pad = p.J3pad;
+    ma.Y = Y; ma.Ypart = p.KS > 1 ? ws + p.off_Yp : nullptr;
+    ma.J1 = s.J[0]; ma.J2 = s.J[1]; ma.J3 = s.J[2]; ma.J1pad = p.J1pad;
+    ma.KS = p.KS; ma.rows_per_split = p.m1_rows_per_split;
+    return dispatch_mode1<MATH>(p, ma, st);
+}
+
+static int validate_shape(const ttm_shape *s) {
+    if (!s) return TTM_ERR_INVALID_ARG;
+    for (int n = 0; n < 3; ++n)
+        if (s->I[n] < 1 || s->J[n] < 1 || s->I[n] > (int64_t(1) << 31) || s->J[n] > (int64_t(1) << 31))
+            return TTM_ERR_INVALID_ARG;
+    if (checked_prod(checked_prod(s->I[0], s->I[1]), s->I[2]) < 0) return TTM_ERR_INVALID_ARG;
+    if (checked_prod(checked_prod(s->J[0], s->J[1]), s->J[2]) < 0) return TTM_ERR_INVALID_ARG;
+    return TTM_OK;
+}
+
+}  // namespace ttm
+
+using namespace ttm;
+
+extern "C" {
+
+int ttm_chain_supported(int x, int f, int y, int m) { return combo_ok(x, f, y, m) ? 1 : 0; }
+
+size_t ttm_chain_workspace_size(const ttm_shape *s, int x_dtype, int math) {
+    if (validate_shape(s) != TTM_OK) return 0;
+    const int f = math == TTM_MATH_F64 ? TTM_F64 : TTM_F32;
+    if (!combo_ok(x_dtype, f, f, math)) return 0;
+    ChainPlan p;
+    if (!make_plan(*s, x_dtype, math, p)) return 0;
+    return p.total;
+}
+
+int ttm_chain(const ttm_shape *s, const void *X, int x_dtype, const void *A, const void *B, const void *C,
+              int f_dtype, void *Y, int y_dtype, int math, void *ws, size_t ws_bytes, void *stream) {
+    int rc = validate_shape(s);
+    if (rc) return rc;
+    if (!combo_ok(x_dtype, f_dtype, y_dtype, math)) return TTM_ERR_UNSUPPORTED;
+    if (!X || !A || !B || !C || !Y) return TTM_ERR_INVALID_ARG;
+    const size_t fs = dtype_size(f_dtype), ys = dtype_size(y_dtype), xs = dtype_size(x_dtype);
+    if (!aligned(X, 16) || !aligned(Y, 16) || !aligned(A, fs) || !aligned(B, fs) || !aligned(C, fs))
+        return TTM_ERR_INVALID_ARG;
+    ChainPlan p;
+    if (!make_plan(*s, x_dtype, math, p)) return TTM_ERR_UNSUPPORTED;
+    if (!ws || ws_bytes < p.total) return TTM_ERR_WORKSPACE;
+    if (!aligned(ws, 16)) return TTM_ERR_INVALID_ARG;
+    const size_t ny = size_t(s->J[0] * s->J[1] * s->J[2]) * ys;
+    const size_t nx = size_t(s->I[0] * s->I[1] * s->I[2]) * xs;
+    if (overlaps(Y, ny, X, nx) || overlaps(Y, ny, A, size_t(s->J[0] * s->I[0]) * fs) ||
+        overlaps(Y, ny, B, size_t(s->J[1] * s->I[1]) * fs) || overlaps(Y, ny, C, size_t(s->J[2] * s->I[2]) * fs) ||
+        overlaps(Y, ny, ws, p.total))
+        return TTM_ERR_ALIAS;
+    if (overlaps(ws, p.total, X, nx) || overlaps(ws, p.total, A, size_t(s->J[0] * s->I[0]) * fs) ||
+        overlaps(ws, p.total, B, size_t(s->J[1] * s->I[1]) * fs) ||
+        overlaps(ws, p.total, C, size_t(s->J[2] * s->I[2]) * fs))
+        return TTM_ERR_ALIAS;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    unsigned char *w = static_cast<unsigned char *>(ws);
+    switch (math) {
+        case TTM_MATH_F64: return run_chain<M_F64>(p, *s, X, A, B, C, Y, w, st);
+        case TTM_MATH_F32: return run_chain<M_F32>(p, *s, X, A, B, C, Y, w, st);
+        case TTM_MATH_BF16: return run_chain<M_BF16>(p, *s, X, A, B, C, Y, w, st);
+        case TTM_MATH_BF16X3: return run_chain<M_BF16X3>(p, *s, X, A, B, C, Y, w, st);
+        default: return TTM_ERR_UNSUPPORTED;
+    }
+}
+
+}  // extern "C"

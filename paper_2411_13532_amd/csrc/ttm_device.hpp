@@ -1,0 +1,137 @@
+// ttm_device.hpp -- device-side building blocks shared by the libttm kernels
+// (gfx950, wave64): number formats, the bfloat16 split, and the matrix-core
+// (MFMA) fragment conventions every contraction kernel uses.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ttm {
+
+enum Math { M_F64 = 0, M_F32 = 1, M_BF16 = 2, M_BF16X3 = 3 };
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// bfloat16 is carried as its 16-bit pattern (the upper half of a float).
+struct bf16_t { uint16_t bits; };
+
+// Round to nearest, ties to even.  NaN stays NaN (quietened); infinities and
+// overflow to infinity follow IEEE rounding.
+__device__ __forceinline__ uint32_t bf16_rne_bits(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+__device__ __forceinline__ float bf16_bits_to_f32(uint32_t h) { return __uint_as_float(h << 16); }
+
+// v = hi + lo + r with hi = rne(v), lo = rne(v - hi); v - hi is exact in float.
+__device__ __forceinline__ void bf16_split(float v, uint32_t &hi, uint32_t &lo) {
+    hi = bf16_rne_bits(v);
+    lo = bf16_rne_bits(v - bf16_bits_to_f32(hi));
+}
+
+__device__ __forceinline__ uint32_t pack2(uint32_t a, uint32_t b) { return a | (b << 16); }
+
+// ---------------------------------------------------------------------------
+// MFMA 16x16 fragment conventions (wave64).
+//
+// For every 16x16 tile shape used here (f64 16x16x4, f32 16x16x4, bf16
+// 16x16x32) a lane l owns row/column (l % 16) of the A/B operand and k-slot
+// group g = l / 16.  Accumulator register r of lane l holds D[row][l % 16]
+// with row = 4*g + r for the f32-accumulating shapes and row = 4*r + g for
+// f64 16x16x4 (acc_row below); both layouts were checked on gfx950 with
+// integer-valued operands.  Which k value a (group, element) slot carries is our choice as
+// long as the A and B operands agree, so a lane always holds k values that are
+// contiguous in memory: one 16-byte load feeds the operand of
+//   bf16: 1 MFMA (8 values),  f32: 4 MFMAs (4 values),  f64: 2 MFMAs (2 values).
+// A "k-group" is the 4 * (values per 16 bytes) k indices one such load covers.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ f32x4 mfma_bf16(u32x4 a, u32x4 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mfma_f32(float a, float b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f64x4 mfma_f64(double a, double b, f64x4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <int MATH> struct MathTraits;
+template <> struct MathTraits<M_F64> {
+    typedef double acc_t; typedef f64x4 accv_t; typedef double fac_t;   // factor storage
+    typedef double lds_t;                                                // operand storage
+    static constexpr int VE = 2;            // values per 16 bytes of operand
+    static constexpr int KG = 4 * VE;       // k indices per k-group
+    __device__ static constexpr int acc_row(int g, int r) { return 4 * r + g; }
+};
+template <> struct MathTraits<M_F32> {
+    typedef float acc_t; typedef f32x4 accv_t; typedef float fac_t; typedef float lds_t;
+    static constexpr int VE = 4;
+    static constexpr int KG = 4 * VE;
+    __device__ static constexpr int acc_row(int g, int r) { return 4 * g + r; }
+};
+template <> struct MathTraits<M_BF16> {
+    typedef float acc_t; typedef f32x4 accv_t; typedef uint16_t fac_t; typedef uint16_t lds_t;
+    static constexpr int VE = 8;
+    static constexpr int KG = 4 * VE;
+    __device__ static constexpr int acc_row(int g, int r) { return 4 * g + r; }
+};
+template <> struct MathTraits<M_BF16X3> : MathTraits<M_BF16> {};
+
+template <typename T> __device__ __forceinline__ T zero_accv();
+template <> __device__ __forceinline__ f32x4 zero_accv<f32x4>() { return f32x4{0.f, 0.f, 0.f, 0.f}; }
+template <> __device__ __forceinline__ f64x4 zero_accv<f64x4>() { return f64x4{0.0, 0.0, 0.0, 0.0}; }
+
+// 16-byte register vector, reinterpretable as 4 floats, 2 doubles or 8 bf16.
+union V16 {
+    u32x4 u;
+    float f[4];
+    double d[2];
+    uint16_t h[8];
+};
+
+__device__ __forceinline__ V16 ld16(const void *p) {
+    V16 v;
+    v.u = *reinterpret_cast<const u32x4 *>(p);
+    return v;
+}
+__device__ __forceinline__ V16 zero16() {
+    V16 v;
+    v.u = u32x4{0u, 0u, 0u, 0u};
+    return v;
+}
+
+// One matrix-core step for a k-group: A and B hold one 16-byte operand
+// fragment each (row/col l%16, values of k-slot group l/16).  For bf16x3 the
+// optional lo fragments add the cross terms hi*lo' + lo*hi'.
+template <int MATH>
+__device__ __forceinline__ void mma_kgroup(typename MathTraits<MATH>::accv_t &acc, const V16 &a, const V16 &b);
+
+template <>
+__device__ __forceinline__ void mma_kgroup<M_F64>(f64x4 &acc, const V16 &a, const V16 &b) {
+    acc = mfma_f64(a.d[0], b.d[0], acc);
+    acc = mfma_f64(a.d[1], b.d[1], acc);
+}
+template <>
+__device__ __forceinline__ void mma_kgroup<M_F32>(f32x4 &acc, const V16 &a, const V16 &b) {
+    acc = mfma_f32(a.f[0], b.f[0], acc);
+    acc = mfma_f32(a.f[1], b.f[1], acc);
+    acc = mfma_f32(a.f[2], b.f[2], acc);
+    acc = mfma_f32(a.f[3], b.f[3], acc);
+}
+template <>
+__device__ __forceinline__ void mma_kgroup<M_BF16>(f32x4 &acc, const V16 &a, const V16 &b) {
+    acc = mfma_bf16(a.u, b.u, acc);
+}
+
+// Host/device rounding helpers for sizes.
+__host__ __device__ constexpr int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ constexpr int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+
+}  // namespace ttm

@@ -1,0 +1,214 @@
+"""PyTorch-facing binding of libttm.
+
+Torch provides device memory and the current HIP stream; every step of the
+chain runs in the library's HIP kernels (see include/ttm.h for the C
+interface these functions wrap one to one).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import MATH, TTM_BF16, TTM_F32, TTM_F64, check
+
+_DT = {torch.float64: TTM_F64, torch.float32: TTM_F32, torch.bfloat16: TTM_BF16}
+
+
+def _ptr(t: torch.Tensor | None):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _need_cuda(*ts):
+    for t in ts:
+        if t is None:
+            continue
+        if not t.is_cuda:
+            raise ValueError("libttm works on GPU tensors only")
+        if not t.is_contiguous():
+            raise ValueError("tensors must be contiguous (row-major)")
+
+
+def _math_id(math: str) -> int:
+    try:
+        return MATH[math]
+    except KeyError:
+        raise ValueError(f"math must be one of {sorted(MATH)}") from None
+
+
+def chain_workspace_size(I, J, x_dtype: torch.dtype, math: str) -> int:
+    s = _lib.shape(I, J)
+    return int(_lib.load().ttm_chain_workspace_size(ctypes.byref(s), _DT[x_dtype], _math_id(math)))
+
+
+def chain(X: torch.Tensor, A: torch.Tensor, B: torch.Tensor, C: torch.Tensor, math: str = "f32",
+          out: torch.Tensor | None = None, workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """Y = X x1 A x2 B x3 C with X (I1,I2,I3) and factors (J_n, I_n), all on one GPU.
+
+    math: "f64" (all float64), "f32", "bf16" or "bf16x3" (float32 factors; X
+    float32 or bfloat16).  Y is float64 for "f64", else float32.
+    """
+    _need_cuda(X, A, B, C, out, workspace)
+    if X.dim() != 3 or A.dim() != 2 or B.dim() != 2 or C.dim() != 2:
+        raise ValueError("X must be 3-way and A, B, C matrices")
+    I = tuple(X.shape)
+    J = (A.shape[0], B.shape[0], C.shape[0])
+    if (A.shape[1], B.shape[1], C.shape[1]) != I:
+        raise ValueError(f"factor widths {A.shape[1], B.shape[1], C.shape[1]} do not match X {I}")
+    m = _math_id(math)
+    ydt = torch.float64 if math == "f64" else torch.float32
+    if out is None:
+        out = torch.empty(J, dtype=ydt, device=X.device)
+    s = _lib.shape(I, J)
+    lib = _lib.load()
+    ws_bytes = int(lib.ttm_chain_workspace_size(ctypes.byref(s), _DT.get(X.dtype, -1), m))
+    if workspace is None:
+        workspace = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=X.device)
+    fdt = _DT.get(A.dtype, -1)
+    if B.dtype != A.dtype or C.dtype != A.dtype:
+        raise ValueError("A, B and C must share one dtype")
+    rc = lib.ttm_chain(ctypes.byref(s), _ptr(X), _DT.get(X.dtype, -1), _ptr(A), _ptr(B), _ptr(C), fdt,
+                       _ptr(out), _DT.get(out.dtype, -1), m, _ptr(workspace), workspace.numel(),
+                       _stream(X.device))
+    check(rc, "ttm_chain")
+    return out
+
+
+def chain_backward_workspace_size(I, J, dtype: torch.dtype, math: str) -> int:
+    s = _lib.shape(I, J)
+    return int(_lib.load().ttm_chain_backward_workspace_size(ctypes.byref(s), _DT[dtype], _math_id(math)))
+
+
+def chain_backward(G, X, A, B, C, math: str = "f32", need=(True, True, True, True), workspace=None):
+    """(dX, dA, dB, dC) for dL/dY = G; entries not in `need` come back as None."""
+    _need_cuda(G, X, A, B, C, workspace)
+    I = tuple(X.shape)
+    J = (A.shape[0], B.shape[0], C.shape[0])
+    if tuple(G.shape) != J:
+        raise ValueError("G must have the output shape")
+    outs = [torch.empty_like(t) if n else None for t, n in zip((X, A, B, C), need)]
+    s = _lib.shape(I, J)
+    lib = _lib.load()
+    m = _math_id(math)
+    ws_bytes = int(lib.ttm_chain_backward_workspace_size(ctypes.byref(s), _DT.get(X.dtype, -1), m))
+    if workspace is None:
+        workspace = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=X.device)
+    rc = lib.ttm_chain_backward(ctypes.byref(s), _ptr(G), _ptr(X), _ptr(A), _ptr(B), _ptr(C),
+                                _DT.get(X.dtype, -1), *[_ptr(o) for o in outs], m,
+                                _ptr(workspace), workspace.numel(), _stream(X.device))
+    check(rc, "ttm_chain_backward")
+    return tuple(outs)
+
+
+class TTMChain(torch.autograd.Function):
+    """Differentiable Y = X x1 A x2 B x3 C whose backward is the library's adjoint kernels."""
+
+    @staticmethod
+    def forward(ctx, X, A, B, C, math="f32"):
+        ctx.save_for_backward(X, A, B, C)
+        ctx.math = math
+        return chain(X.contiguous(), A.contiguous(), B.contiguous(), C.contiguous(), math=math)
+
+    @staticmethod
+    def backward(ctx, G):
+        X, A, B, C = ctx.saved_tensors
+        need = tuple(bool(n) for n in ctx.needs_input_grad[:4])
+        grads = chain_backward(G.contiguous(), X, A, B, C, math=ctx.math, need=need)
+        return (*grads, None)
+
+
+def ttm_chain(X, A, B, C, math="f32"):
+    return TTMChain.apply(X, A, B, C, math)
+
+
+class BatchedPlan:
+    """A ragged batch of independent chains run by one persistent kernel.
+
+    dims: (count, 6) integer array of (I1, I2, I3, J1, J2, J3) per cuboid.
+    Buffers passed to run() are the cuboids' tensors stored back to back.
+    """
+
+    def __init__(self, dims, dtype=torch.float32, tune_cache: str | None = None, device=None):
+        import numpy as np
+        d = np.ascontiguousarray(np.asarray(dims, dtype=np.int64).reshape(-1, 6))
+        self.dims = d
+        self.count = d.shape[0]
+        self.dtype = dtype
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self._lib = _lib.load()
+        h = ctypes.c_void_p()
+        math = "f64" if dtype == torch.float64 else "f32"
+        with torch.cuda.device(self.device):
+            rc = self._lib.ttm_batched_plan_create(
+                self.count, d.ctypes.data_as(ctypes.c_void_p), _DT[dtype], MATH[math],
+                tune_cache.encode() if tune_cache else None, _stream(self.device), ctypes.byref(h))
+        check(rc, "ttm_batched_plan_create")
+        self._h = h
+        tot = (ctypes.c_int64 * 5)()
+        check(self._lib.ttm_batched_plan_totals(h, tot), "ttm_batched_plan_totals")
+        self.totals = tuple(int(v) for v in tot)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib._lib is not None:
+            _lib._lib.ttm_batched_plan_destroy(h)
+            self._h = None
+
+    def empty_output(self):
+        return torch.empty(self.totals[4], dtype=self.dtype, device=self.device)
+
+    def _args(self, X, A, B, C, Y):
+        _need_cuda(X, A, B, C, Y)
+        for t, n in zip((X, A, B, C, Y), self.totals):
+            if t.numel() != n or t.dtype != self.dtype:
+                raise ValueError(f"buffer has {t.numel()} {t.dtype} elements, plan expects {n} {self.dtype}")
+        return [_ptr(t) for t in (X, A, B, C, Y)]
+
+    def run(self, X, A, B, C, Y=None, mode: str = "persistent"):
+        """mode: "persistent" (one launch), "graph" (replay of the plan's HIP graph)
+        or "loop" (one launch per cuboid, for comparison)."""
+        if Y is None:
+            Y = self.empty_output()
+        args = self._args(X, A, B, C, Y)
+        fn = {"persistent": self._lib.ttm_chain_batched, "graph": self._lib.ttm_chain_batched_graph,
+              "loop": self._lib.ttm_chain_batched_loop}[mode]
+        check(fn(self._h, *args, _stream(self.device)), f"ttm_chain_batched[{mode}]")
+        return Y
+
+    def autotune(self, X, A, B, C, Y=None, reps: int = 10) -> float:
+        if Y is None:
+            Y = self.empty_output()
+        args = self._args(X, A, B, C, Y)
+        best = ctypes.c_double()
+        check(self._lib.ttm_batched_autotune(self._h, *args, _stream(self.device), reps, ctypes.byref(best)),
+              "ttm_batched_autotune")
+        return best.value
+
+    def config(self):
+        out = (ctypes.c_int * 3)()
+        check(self._lib.ttm_batched_plan_config(self._h, out), "ttm_batched_plan_config")
+        return {"threads": out[0], "blocks_per_cu": out[1], "blocks": out[2]}
+
+
+def timing_enable(on: bool = True) -> None:
+    check(_lib.load().ttm_timing_enable(1 if on else 0), "ttm_timing_enable")
+
+
+def timing_collect(max_entries: int = 32) -> dict:
+    """{kernel name: (launches, total ms)} since the last collect."""
+    names = ctypes.create_string_buffer(64 * max_entries)
+    counts = (ctypes.c_int64 * max_entries)()
+    ms = (ctypes.c_double * max_entries)()
+    n = _lib.load().ttm_timing_collect(names, counts, ms, max_entries)
+    if n < 0:
+        check(n, "ttm_timing_collect")
+    out = {}
+    for k in range(n):
+        name = names.raw[64 * k:64 * k + 64].split(b"\0", 1)[0].decode()
+        out[name] = (int(counts[k]), float(ms[k]))
+    return out

@@ -1,0 +1,237 @@
+"""Parity of the HIP chain (ttm_chain) against the FP64 oracle.
+
+Tolerances (relative Frobenius error against the FP64 oracle on the exact
+stored inputs): 1e-12 for f64, 1e-5 for f32 and bf16x3, 2e-2 for plain bf16.
+Bitwise checks where the arithmetic is exact (identity factors, small
+integers).  Full-size workloads are checked on a sample of output columns
+j3, which the oracle computes exactly as the chain with the sampled rows of C.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2411_13532_amd import chain, workloads
+from tests import pins
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5, "bf16x3": 1e-5, "bf16": 2e-2}
+DEV = "cuda:0"
+
+
+def to_dev(a, dtype):
+    if isinstance(a, torch.Tensor):
+        return a.to(DEV).to(dtype).contiguous()
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV).to(dtype).contiguous()
+
+
+def int_chain(X, A, B, C):
+    """Exact integer chain (int64 tensordot per mode) for integer-valued data."""
+    Y = np.tensordot(X.astype(np.int64), C.astype(np.int64), axes=([2], [1]))      # [i1][i2][j3]
+    Y = np.tensordot(Y, B.astype(np.int64), axes=([1], [1]))                        # [i1][j3][j2]
+    Y = np.tensordot(Y, A.astype(np.int64), axes=([0], [1]))                        # [j3][j2][j1]
+    return np.transpose(Y, (2, 1, 0)).astype(np.float64)
+
+
+def run(X, A, B, C, math, xdtype=None):
+    fdt = torch.float64 if math == "f64" else torch.float32
+    xdt = xdtype or fdt
+    Xd = to_dev(X, xdt)
+    Y = chain(Xd, to_dev(A, fdt), to_dev(B, fdt), to_dev(C, fdt), math=math)
+    torch.cuda.synchronize()
+    return Y.double().cpu().numpy(), Xd
+
+
+def stored(Xd):
+    """The exact values the GPU consumed, as a float64/float32 numpy array."""
+    if Xd.dtype == torch.bfloat16:
+        return Xd.float().cpu().numpy()
+    return Xd.cpu().numpy()
+
+
+def check_vs_oracle(p, math, xdtype=None, tol=None):
+    Y, Xd = run(p["X"], p["A"], p["B"], p["C"], math, xdtype)
+    fdt = np.float64 if math == "f64" else np.float32
+    ref = oracle.chain(stored(Xd), *(np.asarray(p[k], dtype=fdt) for k in "ABC"))
+    err = pins.rel_fro(Y, ref)
+    print(f"[{math} x={xdtype} I={np.shape(p['X'])} J={ref.shape}] rel err {err:.3e}", flush=True)
+    assert err <= (tol if tol is not None else TOL[math]), err
+    return Y, ref
+
+
+FORMS = [("f64", None), ("f32", None), ("f32", torch.bfloat16), ("bf16", torch.bfloat16),
+         ("bf16", None), ("bf16x3", torch.bfloat16), ("bf16x3", None)]
+FORM_IDS = [f"{m}-x{'bf16' if x is torch.bfloat16 else 'native'}" for m, x in FORMS]
+
+# shapes spanning several row tiles and k chunks with ragged tails, the
+# unaligned (scalar-load) path, wide J (column and j2 tiling), and size-1 modes
+SHAPES = [
+    ((37, 150, 200), (20, 35, 70)),
+    ((3, 260, 136), (130, 140, 150)),
+    ((5, 7, 13), (3, 4, 5)),
+    ((2, 129, 72), (17, 1, 33)),
+    ((1, 1, 1), (1, 1, 1)),
+    ((4, 5, 6), (7, 8, 9)),
+    ((16, 300, 24), (2, 260, 16)),
+]
+
+
+@pytest.mark.parametrize("form", FORMS, ids=FORM_IDS)
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: f"I{s[0]}J{s[1]}")
+def test_chain_ragged_shapes(form, shape):
+    math, xdt = form
+    I, J = shape
+    p = workloads.random_problem(I, J, seed=sum(I) + 7 * sum(J))
+    check_vs_oracle(p, math, xdt)
+
+
+def test_c1_fp64():
+    p = workloads.dense("c1_f64_64_16")
+    check_vs_oracle(p, "f64")
+
+
+@pytest.mark.parametrize("form", FORMS, ids=FORM_IDS)
+def test_identity_factors_bitwise(form):
+    math, xdt = form
+    rng = np.random.default_rng(3)
+    I = (9, 140, 70)
+    X = rng.standard_normal(I)
+    if math in ("bf16", "bf16x3"):
+        X = torch.from_numpy(X.astype(np.float32)).to(torch.bfloat16).float().numpy()  # exactly bf16
+    eye = [np.eye(n) for n in I]
+    Y, Xd = run(X, *eye, math, xdt)
+    assert np.array_equal(Y, stored(Xd).astype(np.float64))
+
+
+@pytest.mark.parametrize("form", FORMS, ids=FORM_IDS)
+def test_exact_integers_bitwise(form):
+    """Small integers: every partial sum is exact on every path (values in
+    {-1,0,1}, I <= 6 keeps plain-bf16 intermediates within 256)."""
+    math, xdt = form
+    rng = np.random.default_rng(5)
+    I, J = (6, 5, 6), (4, 6, 3)
+    X = rng.integers(-1, 2, size=I).astype(np.float64)
+    A, B, C = (rng.integers(-1, 2, size=(J[n], I[n])).astype(np.float64) for n in range(3))
+    Y, _ = run(X, A, B, C, math, xdt)
+    assert np.array_equal(Y, int_chain(X, A, B, C))
+
+
+@pytest.mark.parametrize("math", ["f32", "bf16x3", "f64"])
+def test_exact_integers_one_mode_larger(math):
+    """One nontrivial mode at a time with integer data over several tiles:
+    bitwise on f32/f64 (sums < 2^24) and bf16x3 (intermediates < 2^16)."""
+    rng = np.random.default_rng(6)
+    I = (20, 150, 200)
+    X = rng.integers(-4, 5, size=I).astype(np.float64)
+    for mode in range(3):
+        fs = [np.eye(n) for n in I]
+        fs[mode] = rng.integers(-4, 5, size=(17, I[mode])).astype(np.float64)
+        Y, _ = run(X, *fs, math)
+        assert np.array_equal(Y, int_chain(X, *fs)), mode
+
+
+@pytest.mark.parametrize("form", FORMS, ids=FORM_IDS)
+def test_rank1_closed_form(form):
+    math, xdt = form
+    rng = np.random.default_rng(7)
+    I, J = (33, 140, 90), (12, 40, 70)
+    u, v, w = (rng.standard_normal(I[n]) for n in range(3))
+    X = np.einsum("a,b,c->abc", u, v, w)
+    fs = [rng.standard_normal((J[n], I[n])) / np.sqrt(I[n]) for n in range(3)]
+    Y, Xd = run(X, *fs, math, xdt)
+    # reference from the closed form on the values the GPU consumed
+    fdt = np.float64 if math == "f64" else np.float32
+    fs_st = [f.astype(fdt).astype(np.float64) for f in fs]
+    ref = oracle.chain(stored(Xd), *fs_st)
+    closed = np.einsum("a,b,c->abc", fs_st[0] @ u, fs_st[1] @ v, fs_st[2] @ w)
+    if math == "f64":
+        assert pins.rel_fro(ref, closed) < 1e-13
+    assert pins.rel_fro(Y, ref) <= TOL[math]
+
+
+@pytest.mark.parametrize("n", [8, 12, 13, 64])
+@pytest.mark.parametrize("math", ["f64", "f32", "bf16x3"])
+def test_compact6_closed_form(n, math):
+    """Factors D = A_c^-1 B_c of the paper's compact scheme on periodic grids:
+    sin sin sin maps to k'k'k' cos cos cos exactly.  In f64 the GPU result is
+    compared with the closed form itself; in f32 and bf16x3 with the oracle on
+    the rounded inputs (rounding D to float moves the exact answer by more
+    than the arithmetic tolerance, since D amplifies high wavenumbers)."""
+    sizes = (n, n + 3, n + 5) if n < 64 else (64, 64, 64)
+    modes = (1, 2, 3) if n < 64 else (5, 9, 13)
+    Ds = [pins.compact6_derivative_matrix(k) for k in sizes]
+    xs = [np.arange(k) * (2 * np.pi / k) for k in sizes]
+    X = np.einsum("a,b,c->abc", *[np.sin(m * x) for m, x in zip(modes, xs)])
+    kap = np.prod([pins.compact6_modified_wavenumber(m, k) for m, k in zip(modes, sizes)])
+    closed = kap * np.einsum("a,b,c->abc", *[np.cos(m * x) for m, x in zip(modes, xs)])
+    Y, Xd = run(X, *Ds, math)
+    if math == "f64":
+        assert pins.rel_fro(Y, closed) <= 1e-12
+    else:
+        ref = oracle.chain(stored(Xd), *(D.astype(np.float32) for D in Ds))
+        assert pins.rel_fro(Y, ref) <= TOL[math]
+
+
+@pytest.mark.parametrize("math", ["f32", "bf16x3", "bf16", "f64"])
+def test_deterministic(math):
+    p = workloads.random_problem((40, 300, 96), (30, 50, 70), seed=9)
+    Y1, _ = run(p["X"], p["A"], p["B"], p["C"], math)
+    Y2, _ = run(p["X"], p["A"], p["B"], p["C"], math)
+    assert np.array_equal(Y1, Y2)
+
+
+def test_mode_order_free_operator():
+    """Y computed for (X, A, B, C) equals the chain of the permuted problem
+    (X transposed, factors permuted) transposed back: the library's internal
+    contraction order does not change the operator."""
+    p = workloads.random_problem((20, 36, 50), (8, 9, 10), seed=13)
+    Y, _ = run(p["X"], p["A"], p["B"], p["C"], "f64")
+    Xp = np.ascontiguousarray(np.transpose(p["X"], (2, 0, 1)))
+    Yp, _ = run(Xp, p["C"], p["A"], p["B"], "f64")
+    assert pins.rel_fro(np.transpose(Yp, (1, 2, 0)), Y) < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# Full-size workloads, checked on sampled output columns
+# ---------------------------------------------------------------------------
+def sampled_reference(X_np, A, B, C, cols):
+    """Oracle on Y[:, :, cols] = X x1 A x2 B x3 C[cols, :] (mode 3 first)."""
+    return oracle.chain(X_np, A, B, C[cols, :], order=(3, 2, 1))
+
+
+def test_c2_full_size_fp32():
+    p = workloads.dense("c2_f32_512_64")
+    Xd = to_dev(p["X"], torch.float32)
+    Y = chain(Xd, to_dev(p["A"], torch.float32), to_dev(p["B"], torch.float32), to_dev(p["C"], torch.float32),
+              math="f32")
+    cols = [0, 1, 31, 63]
+    ref = sampled_reference(p["X"], p["A"].astype(np.float64), p["B"].astype(np.float64),
+                            p["C"].astype(np.float64), cols)
+    err = pins.rel_fro(Y[:, :, cols].double().cpu().numpy(), ref)
+    print(f"[c2 f32] sampled rel err {err:.3e}", flush=True)
+    assert err <= 1e-5
+    # orthonormal rows and Gaussian X: entries of Y are N(0,1)
+    var = float(Y.double().var().cpu())
+    assert abs(var - 1.0) < 0.02
+
+
+@pytest.fixture(scope="module")
+def c3_inputs():
+    p = workloads.dense("c3_bf16_1024_128")
+    Xd = p["X"].to(DEV)
+    fs = [to_dev(p[k], torch.float32) for k in "ABC"]
+    X_np = p["X"].float().numpy()
+    cols = [0, 77, 127]
+    ref = sampled_reference(X_np, *(p[k].astype(np.float64) for k in "AB"), p["C"].astype(np.float64), cols)
+    del X_np
+    return Xd, fs, cols, ref
+
+
+@pytest.mark.parametrize("math", ["bf16x3", "bf16", "f32"])
+def test_c3_full_size(c3_inputs, math):
+    Xd, fs, cols, ref = c3_inputs
+    Y = chain(Xd, *fs, math=math)
+    err = pins.rel_fro(Y[:, :, cols].double().cpu().numpy(), ref)
+    print(f"[c3 {math}] sampled rel err {err:.3e}", flush=True)
+    assert err <= TOL[math]
