@@ -120,8 +120,9 @@ int ttm_chain(const ttm_shape *shape,
  *     dA[j1,i1] = sum_{j2,j3} G[j1,j2,j3] (X x2 B x3 C)[i1,j2,j3]
  *     dB[j2,i2] = sum_{j1,j3} G[j1,j2,j3] (X x1 A x3 C)[j1,i2,j3]
  *     dC[j3,i3] = sum_{j1,j2} G[j1,j2,j3] (X x1 A x2 B)[j1,j2,i3]
- * All tensors have one dtype, `dtype` (F64 or F32); math is F64 with F64 and
- * F32 or BF16X3 with F32.  G is [J1][J2][J3]; dX, dA, dB, dC have the shapes
+ * All tensors have one dtype, `dtype`, with math F64 for F64 data and F32 for
+ * F32 data (matrix-core products in that precision).  G is [J1][J2][J3];
+ * dX, dA, dB, dC have the shapes
  * of X, A, B, C and each may be NULL when not wanted (at least one must be
  * given).  Outputs are overwritten (not accumulated) and must not overlap any
  * input, each other, or ws.  Alignment and stream as for ttm_chain.
@@ -137,7 +138,7 @@ int ttm_chain_backward(const ttm_shape *shape, const void *G,
  * persistent kernel launch.
  *
  * dims_host : host array of count x 6 int64, per cuboid (I1,I2,I3,J1,J2,J3),
- *             every entry in [1, 32].
+ *             every entry in [1, 16].
  * dtype     : F32 (math F32) or F64 (math F64).
  * tune_cache: path of a JSON cache of autotuned launch shapes, or NULL.  When
  *             the file holds an entry for this device and workload class it is
@@ -194,11 +195,12 @@ int ttm_batched_plan_config(const ttm_batched_plan *plan, int *out);
 
 /*
  * Per-kernel timing for measurement.  When enabled, every kernel the library
- * launches is bracketed by HIP events recorded on the launch stream.
- * ttm_timing_collect synchronises those events and returns, for up to `max`
- * kernel names, the name (NUL-separated into names, each < 64 bytes), the
- * number of launches and their summed duration in ms; it then clears the
- * record.  Returns the number of entries written, or a negative status.
+ * launches is bracketed by HIP events recorded on the launch stream (do not
+ * enable it while capturing a graph).  ttm_timing_collect synchronises those
+ * events and returns, for up to `max` kernel names, the name (entry n at
+ * names + 64*n, NUL-terminated, so `names` holds 64*max bytes), the number of
+ * launches and their summed duration in ms; it then clears the record.
+ * Returns the number of entries written, or a negative status.
  */
 int ttm_timing_enable(int on);
 int ttm_timing_collect(char *names, int64_t *counts, double *total_ms, int max);

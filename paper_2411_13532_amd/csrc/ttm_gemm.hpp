@@ -1,0 +1,197 @@
+// ttm_gemm.hpp -- a strided matrix-core GEMM used for the unfolded
+// contractions of the adjoint:
+//
+//   Cout[b][m][n] (+)= sum_k opA(m, k) * opB(k, n)
+//   opA(m, k) = A[b*sab + m*sam + ko*sako + ki*saki],   k = ko*Ki + ki
+//   opB(k, n) = sum_{p < P} B[b*sbb + p*sbp + n*sbn + ko*sbko + ki*sbki]
+//
+// The two-level k index lets one call contract a pair of tensor modes whose
+// strides do not merge (an unfolding read in place), and the optional sum over
+// P partials folds a fixed-order reduction into the load.  Tiles of 64 x 64
+// outputs, 4 waves each owning 32 x 32; both operands are staged through LDS
+// in the k-contiguous fragment layout (one 16-byte LDS word per lane and
+// k-group), whatever their strides in memory.  Split-K over grid.y writes
+// per-split partials that a fixed-order reduction sums.
+#pragma once
+#include "ttm_device.hpp"
+
+namespace ttm {
+
+struct GemmArgs {
+    const void *A, *B;
+    void *C;
+    int64_t M, N, K, Ki;
+    int64_t sab, sam, sako, saki;
+    int64_t sbb, sbn, sbko, sbki, sbp;
+    int P;
+    int64_t scb, scm, scn;
+    int64_t k_per_split;   // k range of one grid.y split (multiple of the chunk)
+    int64_t scs;           // stride between split partials in C
+};
+
+template <int MATH>
+struct GemmCfg {
+    typedef MathTraits<MATH> TR;
+    typedef typename TR::lds_t LT;
+    typedef typename TR::acc_t T;
+    static constexpr int VE = TR::VE, KG = TR::KG;
+    static constexpr int KT = 2 * KG;
+    static constexpr int ROWB = KT * int(sizeof(LT)) + 16;
+    static constexpr int TILEB = 64 * ROWB;
+    static constexpr bool SPLIT = (MATH == M_BF16X3);
+    static constexpr int PER = 64 * KT / 256;   // elements per thread per operand tile
+};
+
+template <int MATH>
+__global__ void __launch_bounds__(256) k_gemm(const GemmArgs a) {
+    typedef GemmCfg<MATH> CF;
+    typedef typename CF::T T;
+    typedef typename CF::LT LT;
+    typedef MathTraits<MATH> TR;
+    typedef typename TR::accv_t accv_t;
+    constexpr int KT = CF::KT, KG = CF::KG, PER = CF::PER;
+    // [operand A|B][buffer 0|1][hi|lo]
+    __shared__ __align__(16) unsigned char lds[2 * 2 * CF::TILEB * (CF::SPLIT ? 2 : 1)];
+    auto tile = [&](int op, int buf, int lo) -> unsigned char * {
+        return lds + ((op * 2 + buf) * (CF::SPLIT ? 2 : 1) + lo) * CF::TILEB;
+    };
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int l16 = lane & 15, g = lane >> 4;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int64_t m0 = int64_t(blockIdx.x % ((a.M + 63) / 64)) * 64;
+    const int64_t n0 = int64_t(blockIdx.x / ((a.M + 63) / 64)) * 64;
+    const int64_t b = blockIdx.z;
+    const int64_t kb = int64_t(blockIdx.y) * a.k_per_split;
+    const int64_t ke = a.K < kb + a.k_per_split ? a.K : kb + a.k_per_split;
+    const int64_t nch = ke > kb ? ceil_div(ke - kb, KT) : 0;
+    const T *Ap = static_cast<const T *>(a.A) + b * a.sab;
+    const T *Bp = static_cast<const T *>(a.B) + b * a.sbb;
+
+    // Element e of a thread's share: along k when the operand is k-contiguous
+    // (coalesced k runs), along m/n otherwise (coalesced m/n runs).
+    const bool a_kfast = a.saki == 1;
+    const bool b_kfast = a.sbki == 1;
+    T pa[PER], pb[PER];
+    auto coords = [&](bool kfast, int e, int &r, int &kk) {
+        const int idx = tid + 256 * e;
+        if (kfast) { r = idx / KT; kk = idx % KT; }
+        else { kk = idx / 64; r = idx % 64; }
+    };
+    auto fetch = [&](int64_t ch) {
+        const int64_t k0 = kb + ch * KT;
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            int r, kk;
+            coords(a_kfast, e, r, kk);
+            const int64_t m = m0 + r, k = k0 + kk;
+            T v = T(0);
+            if (m < a.M && k < ke) {
+                const int64_t ko = k / a.Ki, ki = k - ko * a.Ki;
+                v = Ap[m * a.sam + ko * a.sako + ki * a.saki];
+            }
+            pa[e] = v;
+        }
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            int r, kk;
+            coords(b_kfast, e, r, kk);
+            const int64_t n = n0 + r, k = k0 + kk;
+            T v = T(0);
+            if (n < a.N && k < ke) {
+                const int64_t ko = k / a.Ki, ki = k - ko * a.Ki;
+                const T *q = Bp + n * a.sbn + ko * a.sbko + ki * a.sbki;
+                for (int p = 0; p < a.P; ++p) v += q[int64_t(p) * a.sbp];
+            }
+            pb[e] = v;
+        }
+    };
+    auto put = [&](unsigned char *hi, unsigned char *lo, int r, int kk, T v) {
+        const int off = r * CF::ROWB + kk * int(sizeof(LT));
+        if constexpr (MATH == M_BF16 || MATH == M_BF16X3) {
+            uint32_t h, l;
+            bf16_split(v, h, l);
+            *reinterpret_cast<uint16_t *>(hi + off) = uint16_t(h);
+            if constexpr (CF::SPLIT) *reinterpret_cast<uint16_t *>(lo + off) = uint16_t(l);
+        } else {
+            *reinterpret_cast<T *>(hi + off) = v;
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            int r, kk;
+            coords(a_kfast, e, r, kk);
+            put(tile(0, buf, 0), CF::SPLIT ? tile(0, buf, 1) : nullptr, r, kk, pa[e]);
+            coords(b_kfast, e, r, kk);
+            put(tile(1, buf, 0), CF::SPLIT ? tile(1, buf, 1) : nullptr, r, kk, pb[e]);
+        }
+    };
+
+    accv_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = zero_accv<accv_t>();
+
+    if (nch > 0) {
+        fetch(0);
+        store(0);
+    }
+    __syncthreads();
+    for (int64_t ch = 0; ch < nch; ++ch) {
+        if (ch + 1 < nch) fetch(ch + 1);
+        const int buf = int(ch & 1);
+#pragma unroll
+        for (int kg = 0; kg < 2; ++kg) {
+            V16 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int ra = (wm * 32 + i * 16 + l16) * CF::ROWB + kg * 64 + g * 16;
+                const int rb = (wn * 32 + i * 16 + l16) * CF::ROWB + kg * 64 + g * 16;
+                ah[i].u = *reinterpret_cast<const u32x4 *>(tile(0, buf, 0) + ra);
+                bh[i].u = *reinterpret_cast<const u32x4 *>(tile(1, buf, 0) + rb);
+                if constexpr (CF::SPLIT) {
+                    al[i].u = *reinterpret_cast<const u32x4 *>(tile(0, buf, 1) + ra);
+                    bl[i].u = *reinterpret_cast<const u32x4 *>(tile(1, buf, 1) + rb);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    mma_kgroup<MATH == M_BF16X3 ? M_BF16 : MATH>(acc[i][j], ah[i], bh[j]);
+                    if constexpr (CF::SPLIT) {
+                        mma_kgroup<M_BF16>(acc[i][j], ah[i], bl[j]);
+                        mma_kgroup<M_BF16>(acc[i][j], al[i], bh[j]);
+                    }
+                }
+        }
+        if (ch + 1 < nch) store(buf ^ 1);
+        __syncthreads();
+    }
+
+    T *Cp = static_cast<T *>(a.C) + b * a.scb + int64_t(blockIdx.y) * a.scs;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t m = m0 + wm * 32 + i * 16 + TR::acc_row(g, r);
+                const int64_t n = n0 + wn * 32 + j * 16 + l16;
+                if (m < a.M && n < a.N) Cp[m * a.scm + n * a.scn] = acc[i][j][r];
+            }
+}
+
+// out[e] = sum_{s < S} part[s * stride + e], increasing s.
+template <typename T>
+__global__ void __launch_bounds__(256) k_sum_splits(const T *part, int64_t stride, int S, int64_t n, T *out) {
+    for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < n; e += int64_t(gridDim.x) * 256) {
+        T s = T(0);
+        for (int k = 0; k < S; ++k) s += part[int64_t(k) * stride + e];
+        out[e] = s;
+    }
+}
+
+}  // namespace ttm
