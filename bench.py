@@ -1,0 +1,307 @@
+"""Throughput of the TTM chain on one MI355X, printed as one JSON line.
+
+Default workload (the precision form of the chain):
+  X 1024 x 1024 x 1024 stored bfloat16 (seeded N(0,1) float32, rounded to
+  nearest even), factors A, B, C 128 x 1024 float32 with orthonormal rows,
+  Y = X x1 A x2 B x3 C computed with split-precision bf16x3 matrix-core
+  products.  The same inputs are also run in plain float32 and plain bfloat16;
+  the line reports each form's time, its relative Frobenius error against the
+  FP64 oracle on a sample of output columns, and the bf16x3 / float32 speedup.
+
+A step is one full chain (factor preparation, the fused mode-3/mode-2 slab
+kernel, the mode-1 kernel) on inputs already resident in HBM.  `value` is the
+useful GFLOP/s, 2 (J I^3 + J^2 I^2 + J^3 I) per chain; split-precision extra
+products are not counted.  `roofline` is for the dominant kernel (the slab
+kernel), timed with HIP events recorded by the library on the launch stream.
+
+Other workloads: --workload c2 (X 512^3 float32, J = 64, float32),
+c4 (20000 ragged cuboids), c5 (X 256^3 float32, J = 32, forward + adjoint).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+MFMA_BF16_TFLOPS = 2516.6      # dense bf16 matrix cores
+F32_TFLOPS = 157.3             # fp32 (matrix and vector)
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def chain_flops(I, J):
+    return 2.0 * (J * I ** 3 + J * J * I * I + J ** 3 * I)
+
+
+def kernel_src_sha():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2411_13532_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(tag, per_launch_units=1.0):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when there is none or the kernels changed since it was taken."""
+    path = os.path.join(PROFILES, f"{tag}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_src_sha") != kernel_src_sha():
+        return None
+    return float(t["bytes_per_launch"]) * per_launch_units
+
+
+def timed(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / steps, wall
+
+
+def kernel_times(fn, steps, torch, ttm):
+    """Average duration (ms) of each library kernel over `steps` calls."""
+    ttm.timing_enable(True)
+    ttm.timing_collect()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    t = ttm.timing_collect()
+    ttm.timing_enable(False)
+    return {k: v[1] / v[0] for k, v in t.items()}
+
+
+def rel_err(y, ref):
+    return float(np.linalg.norm((y - ref).ravel()) / np.linalg.norm(ref.ravel()))
+
+
+def bench_dense_precision(args, torch, ttm):
+    from paper_2411_13532_amd import workloads
+    I, J = 1024, 128
+    t_gen = time.perf_counter()
+    p = workloads.dense("c3_bf16_1024_128")
+    print(f"# inputs generated in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
+    dev = "cuda:0"
+    X = p["X"].to(dev)
+    fs = [torch.from_numpy(p[k]).to(dev) for k in "ABC"]
+    flops = chain_flops(I, J)
+    out = {}
+    forms = {}
+    Ys = {}
+    for math, steps in (("bf16x3", args.steps), ("f32", max(3, args.steps // 4)), ("bf16", args.steps)):
+        wsm = torch.empty(ttm.chain_workspace_size((I,) * 3, (J,) * 3, torch.bfloat16, math), dtype=torch.uint8,
+                          device=dev)
+        Y = torch.empty((J, J, J), dtype=torch.float32, device=dev)
+        fn = lambda: ttm.chain(X, *fs, math=math, out=Y, workspace=wsm)
+        ms, wall = timed(fn, steps, args.warmup, torch)
+        kt = kernel_times(fn, min(steps, 10), torch, ttm)
+        forms[math] = {"ms_per_step": ms, "gflops": flops / (ms * 1e-3) / 1e9, "steps": steps,
+                       "kernel_ms": {k: round(v, 4) for k, v in kt.items()}}
+        Ys[math] = Y.clone()
+        print(f"# {math}: {ms:.3f} ms/step, kernels {kt}", file=sys.stderr, flush=True)
+        if math == "bf16x3":
+            out["ms"], out["wall"], out["kernels"] = ms, wall, kt
+    # oracle on a bounded sample (two output columns j3): the CPU baseline and
+    # the accuracy of every form
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        cols = [0, 77]
+        X_np = p["X"].float().numpy()
+        A64, B64, C64 = (p[k].astype(np.float64) for k in "ABC")
+        t0 = time.perf_counter()
+        ref = oracle.chain(X_np, A64, B64, C64[cols, :], order=(3, 2, 1))
+        dt = time.perf_counter() - t0
+        sample_flops = 2.0 * (len(cols) * I ** 3 + J * len(cols) * I * I + J * J * len(cols) * I)
+        cpu = {"value": sample_flops / dt / 1e9, "unit": "GFLOP/s", "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": f"Y[:, :, j3 in {cols}] of the 1024^3 workload (the chain with 2 of the 128 rows of C; "
+                         f"all of X read), {sample_flops / 1e9:.2f} GFLOP in {dt:.1f} s"}
+        for math, Y in Ys.items():
+            forms[math]["rel_err_vs_oracle"] = rel_err(Y[:, :, cols].double().cpu().numpy(), ref)
+        del X_np
+    # dominant kernel: the slab kernel (modes 3 and 2); algorithmic bytes are
+    # X (bf16) + the partial V it writes (float) + the factor operands it reads
+    slab_ms = out["kernels"]["ttm_slab"]
+    x_bytes = I ** 3 * 2
+    v_bytes = I * J * J * 4
+    fac_bytes = 2 * (J * I * 4)            # B and C as bf16 hi + lo
+    slab_bytes = x_bytes + v_bytes + fac_bytes
+    slab_mfma = 2 * (2.0 * J * I ** 3) + 3 * (2.0 * J * J * I * I)
+    gbs = slab_bytes / (slab_ms * 1e-3) / 1e9
+    tflops = slab_mfma / (slab_ms * 1e-3) / 1e12
+    t_hbm = slab_bytes / (HBM_PEAK_GBS * 1e9)
+    t_mfma = slab_mfma / (MFMA_BF16_TFLOPS * 1e12)
+    if t_hbm >= t_mfma:
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    else:
+        roof = {"bound": "mfma", "achieved": round(tflops, 1), "peak": MFMA_BF16_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(tflops / MFMA_BF16_TFLOPS, 4)}
+    roof["traffic"] = measured_traffic("ttm_slab_c3_bf16x3")
+    roof["kernel"] = "ttm_slab (k_slab<bf16x3, bf16 X, 4 waves x 32 columns, 8 j2 blocks>)"
+    roof["kernel_ms"] = round(slab_ms, 4)
+    roof["algorithmic_bytes"] = slab_bytes
+    roof["mfma_flops"] = slab_mfma
+    roof["mfma_frac"] = round(tflops / MFMA_BF16_TFLOPS, 4)
+    ms = out["ms"]
+    line = {
+        "metric": "TTM-chain GFLOP/s + % roofline; bf16x3 vs FP32 speedup at rel err<=1e-5",
+        "value": round(flops / (ms * 1e-3) / 1e9, 1),
+        "unit": "GFLOP/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16x3", "data": "synthetic",
+        "config": {"workload": "X 1024^3 bfloat16 N(0,1) seed 2; A,B,C 128x1024 float32 orthonormal rows; "
+                               "Y = X x1 A x2 B x3 C, split-precision bf16x3",
+                   "I": I, "J": J, "x_dtype": "bf16", "math": "bf16x3", "parallelism": "single GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "forms": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                  for k, v in forms.items()},
+        "bf16x3_vs_f32_speedup": round(forms["f32"]["ms_per_step"] / forms["bf16x3"]["ms_per_step"], 3),
+    }
+    return line
+
+
+def bench_c2(args, torch, ttm):
+    from paper_2411_13532_amd import workloads
+    I, J = 512, 64
+    p = workloads.dense("c2_f32_512_64")
+    dev = "cuda:0"
+    X = torch.from_numpy(p["X"]).to(dev)
+    fs = [torch.from_numpy(p[k]).to(dev) for k in "ABC"]
+    res = {}
+    for math in ("f32", "bf16x3"):
+        ws = torch.empty(ttm.chain_workspace_size((I,) * 3, (J,) * 3, torch.float32, math), dtype=torch.uint8, device=dev)
+        Y = torch.empty((J, J, J), dtype=torch.float32, device=dev)
+        fn = lambda: ttm.chain(X, *fs, math=math, out=Y, workspace=ws)
+        ms, _ = timed(fn, args.steps, args.warmup, torch)
+        res[math] = {"ms_per_step": ms, "gflops": chain_flops(I, J) / (ms * 1e-3) / 1e9,
+                     "kernel_ms": kernel_times(fn, 10, torch, ttm)}
+    ms = res["f32"]["ms_per_step"]
+    slab = res["f32"]["kernel_ms"]["ttm_slab"]
+    slab_flops = 2.0 * J * I ** 3 + 2.0 * J * J * I * I
+    tf = slab_flops / (slab * 1e-3) / 1e12
+    return {"metric": "TTM-chain GFLOP/s + % roofline", "value": round(chain_flops(I, J) / (ms * 1e-3) / 1e9, 1),
+            "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "X 512^3 float32 N(0,1) seed 1; A,B,C 64x512 orthonormal rows; float32",
+                       "I": I, "J": J},
+            "roofline": {"bound": "mfma", "achieved": round(tf, 1), "peak": F32_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(tf / F32_TFLOPS, 4), "traffic": None, "kernel": "ttm_slab", "kernel_ms": slab},
+            "forms": res}
+
+
+def bench_c4(args, torch, ttm):
+    from paper_2411_13532_amd import BatchedPlan, workloads
+    p = workloads.batched()
+    dev = "cuda:0"
+    bufs = [torch.from_numpy(p[k]).to(dev) for k in "XABC"]
+    plan = BatchedPlan(p["dims"], dtype=torch.float32)
+    Y = plan.empty_output()
+    flops = float(np.sum(6.0 * p["dims"][:, 0].astype(np.float64) ** 4))
+    nbytes = 4.0 * sum(b.numel() for b in bufs) + 4.0 * Y.numel()
+    flush = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
+    best = plan.autotune(*bufs, Y=Y, reps=5)
+
+    def cold(mode):
+        flush.fill_(1)   # evict the 256 MB last-level cache between steps
+        plan.run(*bufs, Y=Y, mode=mode)
+
+    res = {}
+    for mode in ("persistent", "graph"):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        tot = 0.0
+        for _ in range(args.warmup):
+            cold(mode)
+        for _ in range(args.steps):
+            flush.fill_(1)
+            e0.record()
+            plan.run(*bufs, Y=Y, mode=mode)
+            e1.record()
+            torch.cuda.synchronize()
+            tot += e0.elapsed_time(e1)
+        res[mode] = tot / args.steps
+    ms_loop, _ = timed(lambda: plan.run(*bufs, Y=Y, mode="loop"), 2, 1, torch)
+    ms = res["graph"]
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"metric": "batched TTM-chain GFLOP/s + % roofline", "value": round(flops / (ms * 1e-3) / 1e9, 1),
+            "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "20000 cuboids n^3, n ~ U{5..13} seed 3, square factors N(0,1/n); float32",
+                       "count": 20000, "config": plan.config(), "autotune_best_ms": best},
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "ttm_batched"},
+            "persistent_ms": round(res["persistent"], 5), "graph_ms": round(res["graph"], 5),
+            "per_cuboid_loop_ms": round(ms_loop, 3), "loop_over_graph": round(ms_loop / ms, 1)}
+
+
+def bench_c5(args, torch, ttm):
+    from paper_2411_13532_amd import workloads
+    I, J = 256, 32
+    p = workloads.dense("c5_f32_256_32")
+    dev = "cuda:0"
+    X, A, B, C, T = (torch.from_numpy(p[k]).to(dev) for k in "XABCT")
+    Y = torch.empty((J, J, J), dtype=torch.float32, device=dev)
+    fwd = lambda: ttm.chain(X, A, B, C, math="f32", out=Y)
+    ms_f, _ = timed(fwd, args.steps, args.warmup, torch)
+    G = Y - T
+    bwd = lambda: ttm.chain_backward(G, X, A, B, C, math="f32")
+    ms_b, _ = timed(bwd, args.steps, args.warmup, torch)
+    fl_f = chain_flops(I, J)
+    return {"metric": "TTM-chain forward+adjoint GFLOP/s", "value": round(fl_f / ((ms_f) * 1e-3) / 1e9, 1),
+            "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(ms_f + ms_b, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "X 256^3 float32, factors 32x256 N(0,1/256), L = 1/2||Y - T||^2", "I": I, "J": J},
+            "forward_ms": round(ms_f, 4), "backward_ms": round(ms_b, 4),
+            "backward_kernels_ms": kernel_times(bwd, 5, torch, ttm)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c4", "c5"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2411_13532_amd as ttm
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.init()
+    fn = {"c3": bench_dense_precision, "c2": bench_c2, "c4": bench_c4, "c5": bench_c5}[args.workload]
+    line = fn(args, torch, ttm)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

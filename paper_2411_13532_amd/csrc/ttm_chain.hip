@@ -30,7 +30,18 @@ struct PrepArgs {
     void *hi[3];
     void *lo[3];
     int64_t J[3], I[3], Jpad[3], ld[3];
+    int perm32[3];   // 1: store columns in the mode-2 operand order (see below)
 };
+
+// Column position of source column c in a mode-2 bf16 operand row.  Inside
+// every aligned block of 32 columns, accumulator rows 4g..4g+3 of the first
+// 16-row block and 4g..4g+3 of the second one are the 8 k values of lane
+// group g (slab_mode2); storing them next to each other lets one 16-byte
+// load fetch the whole fragment.
+__host__ __device__ inline int64_t mode2_col(int64_t c) {
+    const int64_t q = c & 31, base = c - q;
+    return q < 16 ? base + 8 * (q >> 2) + (q & 3) : base + 8 * ((q - 16) >> 2) + 4 + (q & 3);
+}
 
 // Factor n of shape J x I (row-major, float or double) -> padded Jpad x ld
 // operand array(s).  For bfloat16 operands `hi` gets rne(v) and `lo` (when
@@ -47,8 +58,9 @@ __global__ void __launch_bounds__(256) k_prep_factors(PrepArgs a) {
             const float v = in ? float(src[r * a.I[f] + c]) : 0.f;
             uint32_t h, l;
             bf16_split(v, h, l);
-            static_cast<uint16_t *>(a.hi[f])[e] = uint16_t(h);
-            if (a.lo[f]) static_cast<uint16_t *>(a.lo[f])[e] = uint16_t(l);
+            const int64_t dst = a.perm32[f] ? r * a.ld[f] + mode2_col(c) : e;
+            static_cast<uint16_t *>(a.hi[f])[dst] = uint16_t(h);
+            if (a.lo[f]) static_cast<uint16_t *>(a.lo[f])[dst] = uint16_t(l);
         } else {
             typedef typename MathTraits<MATH>::fac_t FT;
             static_cast<FT *>(a.hi[f])[e] = in ? FT(src[r * a.I[f] + c]) : FT(0);
@@ -80,13 +92,17 @@ template <typename XT, typename LT> struct XGroup;
 template <typename T> struct XGroup<T, T> {          // same type: one 16-byte load
     static constexpr int VE = 16 / sizeof(T);
     V16 raw;
-    __device__ void fetch(const T *row, int64_t k, int64_t I3, bool valid, bool vec) {
-        if (!valid || k >= I3) { raw = zero16(); return; }
-        if (vec) { raw = ld16(row + k); return; }
+    // row: this group's row of X; ok: row and k in range; safe: any valid address
+    __device__ void fetch(const T *row, int64_t k, int64_t I3, bool ok, bool vec, const T *safe) {
+        if (vec) {
+            raw = ld16(ok ? row + k : safe);
+            if (!ok) raw = zero16();
+            return;
+        }
         T tmp[VE];
 #pragma unroll
-        for (int e = 0; e < VE; ++e) tmp[e] = (k + e < I3) ? row[k + e] : T(0);
-        raw = *reinterpret_cast<V16 *>(tmp);
+        for (int e = 0; e < VE; ++e) tmp[e] = (ok && k + e < I3) ? row[k + e] : T(0);
+        __builtin_memcpy(&raw, tmp, 16);
     }
     __device__ void store(unsigned char *hi, unsigned char *) const { *reinterpret_cast<u32x4 *>(hi) = raw.u; }
 };
@@ -94,12 +110,15 @@ template <typename T> struct XGroup<T, T> {          // same type: one 16-byte l
 template <> struct XGroup<uint16_t, float> {        // bf16 X, float operands: 8-byte load
     static constexpr int VE = 4;
     u32x2 raw;
-    __device__ void fetch(const uint16_t *row, int64_t k, int64_t I3, bool valid, bool vec) {
-        if (!valid || k >= I3) { raw = u32x2{0u, 0u}; return; }
-        if (vec) { raw = *reinterpret_cast<const u32x2 *>(row + k); return; }
+    __device__ void fetch(const uint16_t *row, int64_t k, int64_t I3, bool ok, bool vec, const uint16_t *safe) {
+        if (vec) {
+            raw = *reinterpret_cast<const u32x2 *>(ok ? row + k : safe);
+            if (!ok) raw = u32x2{0u, 0u};
+            return;
+        }
         uint32_t h[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) h[e] = (k + e < I3) ? row[k + e] : 0u;
+        for (int e = 0; e < 4; ++e) h[e] = (ok && k + e < I3) ? row[k + e] : 0u;
         raw = u32x2{pack2(h[0], h[1]), pack2(h[2], h[3])};
     }
     __device__ void store(unsigned char *hi, unsigned char *) const {
@@ -115,24 +134,26 @@ template <> struct XGroup<uint16_t, float> {        // bf16 X, float operands: 8
 template <> struct XGroup<float, uint16_t> {        // float X, bf16 operands: 32-byte load, split on store
     static constexpr int VE = 8;
     V16 raw0, raw1;
-    __device__ void fetch(const float *row, int64_t k, int64_t I3, bool valid, bool vec) {
-        if (!valid || k >= I3) { raw0 = zero16(); raw1 = zero16(); return; }
-        if (vec) { raw0 = ld16(row + k); raw1 = ld16(row + k + 4); return; }
+    __device__ void fetch(const float *row, int64_t k, int64_t I3, bool ok, bool vec, const float *safe) {
+        if (vec) {
+            const float *p = ok ? row + k : safe;
+            raw0 = ld16(p);
+            raw1 = ld16(p + 4);
+            if (!ok) { raw0 = zero16(); raw1 = zero16(); }
+            return;
+        }
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            raw0.f[e] = (k + e < I3) ? row[k + e] : 0.f;
-            raw1.f[e] = (k + 4 + e < I3) ? row[k + 4 + e] : 0.f;
+            raw0.f[e] = (ok && k + e < I3) ? row[k + e] : 0.f;
+            raw1.f[e] = (ok && k + 4 + e < I3) ? row[k + 4 + e] : 0.f;
         }
     }
     __device__ void store(unsigned char *hi, unsigned char *lo) const {
-        uint32_t h[8], l[8];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            bf16_split(raw0.f[e], h[e], l[e]);
-            bf16_split(raw1.f[e], h[4 + e], l[4 + e]);
-        }
-        *reinterpret_cast<u32x4 *>(hi) = u32x4{pack2(h[0], h[1]), pack2(h[2], h[3]), pack2(h[4], h[5]), pack2(h[6], h[7])};
-        if (lo) *reinterpret_cast<u32x4 *>(lo) = u32x4{pack2(l[0], l[1]), pack2(l[2], l[3]), pack2(l[4], l[5]), pack2(l[6], l[7])};
+        const float v[8] = {raw0.f[0], raw0.f[1], raw0.f[2], raw0.f[3], raw1.f[0], raw1.f[1], raw1.f[2], raw1.f[3]};
+        u32x4 h, l;
+        bf16_split8(v, h, lo ? &l : nullptr);
+        *reinterpret_cast<u32x4 *>(hi) = h;
+        if (lo) *reinterpret_cast<u32x4 *>(lo) = l;
     }
 };
 
@@ -188,7 +209,8 @@ __device__ __forceinline__ void slab_mode2(typename MathTraits<MATH>::accv_t (&v
         }
     } else {
         // bf16: two stacked 16-row blocks give a lane the 8 values
-        // {W[32p + 4g + e], W[32p + 16 + 4g + e]}, e = 0..3 -> one k-slot group.
+        // {W[32p + 4g + e], W[32p + 16 + 4g + e]}, e = 0..3 -> one k-slot group;
+        // the B operand stores those 8 columns contiguously (mode2_col).
         const uint16_t *Bh = static_cast<const uint16_t *>(a.Bhi);
         const uint16_t *Bl = static_cast<const uint16_t *>(a.Blo);
 #pragma unroll
@@ -196,42 +218,27 @@ __device__ __forceinline__ void slab_mode2(typename MathTraits<MATH>::accv_t (&v
             u32x4 wh[NBW], wl[NBW];
 #pragma unroll
             for (int nb = 0; nb < NBW; ++nb) {
-                uint32_t h[8], l[8];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    if constexpr (MATH == M_BF16X3) {
-                        bf16_split(wacc[2 * p][nb][e], h[e], l[e]);
-                        bf16_split(wacc[2 * p + 1][nb][e], h[4 + e], l[4 + e]);
-                    } else {
-                        h[e] = bf16_rne_bits(wacc[2 * p][nb][e]);
-                        h[4 + e] = bf16_rne_bits(wacc[2 * p + 1][nb][e]);
-                        l[e] = l[4 + e] = 0;
-                    }
-                }
-                wh[nb] = u32x4{pack2(h[0], h[1]), pack2(h[2], h[3]), pack2(h[4], h[5]), pack2(h[6], h[7])};
-                wl[nb] = u32x4{pack2(l[0], l[1]), pack2(l[2], l[3]), pack2(l[4], l[5]), pack2(l[6], l[7])};
+                const float v[8] = {wacc[2 * p][nb][0], wacc[2 * p][nb][1], wacc[2 * p][nb][2], wacc[2 * p][nb][3],
+                                    wacc[2 * p + 1][nb][0], wacc[2 * p + 1][nb][1], wacc[2 * p + 1][nb][2],
+                                    wacc[2 * p + 1][nb][3]};
+                if constexpr (MATH == M_BF16X3) bf16_split8(v, wh[nb], &wl[nb]);
+                else wh[nb] = bf16_round8(v);
             }
 #pragma unroll
             for (int jb = 0; jb < JB; ++jb) {
-                {
-                    const int64_t off = int64_t((jbase + jb) * 16 + l16) * a.ldb + wrow0 + 32 * p + 4 * g;
-                    const u32x2 h0 = *reinterpret_cast<const u32x2 *>(Bh + off);
-                    const u32x2 h1 = *reinterpret_cast<const u32x2 *>(Bh + off + 16);
-                    const u32x4 bh = u32x4{h0[0], h0[1], h1[0], h1[1]};
-                    if constexpr (MATH == M_BF16X3) {
-                        const u32x2 l0 = *reinterpret_cast<const u32x2 *>(Bl + off);
-                        const u32x2 l1 = *reinterpret_cast<const u32x2 *>(Bl + off + 16);
-                        const u32x4 bl = u32x4{l0[0], l0[1], l1[0], l1[1]};
+                const int64_t off = int64_t((jbase + jb) * 16 + l16) * a.ldb + wrow0 + 32 * p + 8 * g;
+                const u32x4 bh = ld16(Bh + off).u;
+                if constexpr (MATH == M_BF16X3) {
+                    const u32x4 bl = ld16(Bl + off).u;
 #pragma unroll
-                        for (int nb = 0; nb < NBW; ++nb) {
-                            vacc[jb][nb] = mfma_bf16(bh, wh[nb], vacc[jb][nb]);
-                            vacc[jb][nb] = mfma_bf16(bh, wl[nb], vacc[jb][nb]);
-                            vacc[jb][nb] = mfma_bf16(bl, wh[nb], vacc[jb][nb]);
-                        }
-                    } else {
-#pragma unroll
-                        for (int nb = 0; nb < NBW; ++nb) vacc[jb][nb] = mfma_bf16(bh, wh[nb], vacc[jb][nb]);
+                    for (int nb = 0; nb < NBW; ++nb) {
+                        vacc[jb][nb] = mfma_bf16(bh, wh[nb], vacc[jb][nb]);
+                        vacc[jb][nb] = mfma_bf16(bh, wl[nb], vacc[jb][nb]);
+                        vacc[jb][nb] = mfma_bf16(bl, wh[nb], vacc[jb][nb]);
                     }
+                } else {
+#pragma unroll
+                    for (int nb = 0; nb < NBW; ++nb) vacc[jb][nb] = mfma_bf16(bh, wh[nb], vacc[jb][nb]);
                 }
             }
             __builtin_amdgcn_sched_barrier(0);
@@ -285,15 +292,15 @@ __global__ void __launch_bounds__(SLAB_THREADS, 2) k_slab(const SlabArgs a) {
         for (int nb = 0; nb < NBW; ++nb) vacc[jb][nb] = zero_accv<accv_t>();
 
     XGroup<XT, LT> pre[GROUPS];
-    auto fetch = [&](int64_t q) {
-        const int64_t t = q / nk, kc = q % nk;
+    auto fetch = [&](int64_t t, int64_t kc) {
         const int64_t r0 = row_begin + t * SLAB_TM;
 #pragma unroll
         for (int j = 0; j < GROUPS; ++j) {
             const int gi = tid + SLAB_THREADS * j;
             const int r = gi >> 3, cg = gi & 7;
             const int64_t grow = r0 + r;
-            pre[j].fetch(Xs + grow * a.I3, kc * KC + cg * VE, a.I3, grow < row_end, vec);
+            const int64_t k = kc * KC + cg * VE;
+            pre[j].fetch(Xs + grow * a.I3, k, a.I3, grow < row_end && k < a.I3, vec, Xs);
         }
     };
     auto store = [&](int buf) {
@@ -305,17 +312,18 @@ __global__ void __launch_bounds__(SLAB_THREADS, 2) k_slab(const SlabArgs a) {
             pre[j].store(tile_hi + off, CF::XLO ? tile_lo + off : nullptr);
         }
     };
-
     const FT *Ch = static_cast<const FT *>(a.Chi);
     const FT *Cl = static_cast<const FT *>(a.Clo);
 
     if (nq > 0) {
-        fetch(0);
+        fetch(0, 0);
         store(0);
     }
     __syncthreads();
 
     int64_t q = 0;
+    int64_t ft = 0, fkc = 1;   // chunk fetched next (tile, k chunk)
+    if (fkc == nk) { fkc = 0; ft = 1; }
     for (int64_t t = 0; t < ntiles; ++t) {
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
@@ -323,7 +331,8 @@ __global__ void __launch_bounds__(SLAB_THREADS, 2) k_slab(const SlabArgs a) {
             for (int nb = 0; nb < NBW; ++nb) wacc[mb][nb] = zero_accv<accv_t>();
 
         for (int64_t kc = 0; kc < nk; ++kc, ++q) {
-            if (q + 1 < nq) fetch(q + 1);
+            const bool more = q + 1 < nq;
+            if (more) fetch(ft, fkc);
 
             const int buf = int(q & 1);
 #pragma unroll
@@ -354,7 +363,10 @@ __global__ void __launch_bounds__(SLAB_THREADS, 2) k_slab(const SlabArgs a) {
                     }
                 }
             }
-            if (q + 1 < nq) store(buf ^ 1);
+            if (more) {
+                store(buf ^ 1);
+                if (++fkc == nk) { fkc = 0; ++ft; }
+            }
             __syncthreads();
         }
         const int64_t wrow0 = row_begin + t * SLAB_TM + wr * RW;
@@ -463,17 +475,16 @@ __global__ void __launch_bounds__(256) k_mode1(const Mode1Args a) {
             } else if constexpr (MATH == M_F64) {
                 *reinterpret_cast<f64x2 *>(lhi + off) = f64x2{pre[it][0], pre[it][1]};
             } else {
-                uint32_t h[8], l[8];
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    if constexpr (MATH == M_BF16X3) bf16_split(pre[it][e], h[e], l[e]);
-                    else { h[e] = bf16_rne_bits(pre[it][e]); l[e] = 0; }
+                const float v[8] = {pre[it][0], pre[it][1], pre[it][2], pre[it][3],
+                                    pre[it][4], pre[it][5], pre[it][6], pre[it][7]};
+                u32x4 h, l;
+                if constexpr (CF::SPLIT) {
+                    bf16_split8(v, h, &l);
+                    *reinterpret_cast<u32x4 *>(llo + off) = l;
+                } else {
+                    h = bf16_round8(v);
                 }
-                *reinterpret_cast<u32x4 *>(lhi + off) =
-                    u32x4{pack2(h[0], h[1]), pack2(h[2], h[3]), pack2(h[4], h[5]), pack2(h[6], h[7])};
-                if constexpr (CF::SPLIT)
-                    *reinterpret_cast<u32x4 *>(llo + off) =
-                        u32x4{pack2(l[0], l[1]), pack2(l[2], l[3]), pack2(l[4], l[5]), pack2(l[6], l[7])};
+                *reinterpret_cast<u32x4 *>(lhi + off) = h;
             }
         }
     };
@@ -745,6 +756,7 @@ static int run_chain(const ChainPlan &p, const ttm_shape &s, const void *X, cons
         pa.I[f] = s.I[f];
         pa.Jpad[f] = Jpad[f];
         pa.ld[f] = ld[f];
+        pa.perm32[f] = (f == 1 && (MATH == M_BF16 || MATH == M_BF16X3)) ? 1 : 0;
         maxn = std::max<int64_t>(maxn, Jpad[f] * ld[f]);
     }
     dim3 pgrid(unsigned(std::min<int64_t>(ceil_div(maxn, 256), 4096)), 3);

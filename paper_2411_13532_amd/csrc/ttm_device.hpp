@@ -19,20 +19,37 @@ typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 // bfloat16 is carried as its 16-bit pattern (the upper half of a float).
 struct bf16_t { uint16_t bits; };
 
-// Round to nearest, ties to even.  NaN stays NaN (quietened); infinities and
-// overflow to infinity follow IEEE rounding.
-__device__ __forceinline__ uint32_t bf16_rne_bits(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return u >> 16;
+// float -> bfloat16 conversions use the gfx950 converter (v_cvt_pk_bf16_f32),
+// which rounds to nearest with ties to even (the default rounding mode) and
+// keeps NaN a NaN; two values per instruction, first value in the low half.
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t cvt_pk_bf16(float a, float b) {
+    bf16x2_t v = {static_cast<__bf16>(a), static_cast<__bf16>(b)};
+    return __builtin_bit_cast(uint32_t, v);
 }
+__device__ __forceinline__ uint32_t bf16_rne_bits(float f) { return cvt_pk_bf16(f, 0.f) & 0xffffu; }
 __device__ __forceinline__ float bf16_bits_to_f32(uint32_t h) { return __uint_as_float(h << 16); }
 
 // v = hi + lo + r with hi = rne(v), lo = rne(v - hi); v - hi is exact in float.
 __device__ __forceinline__ void bf16_split(float v, uint32_t &hi, uint32_t &lo) {
     hi = bf16_rne_bits(v);
     lo = bf16_rne_bits(v - bf16_bits_to_f32(hi));
+}
+// The same for a pair (a in the low half): packed hi and packed lo.
+__device__ __forceinline__ void bf16_split2(float a, float b, uint32_t &hi, uint32_t &lo) {
+    hi = cvt_pk_bf16(a, b);
+    lo = cvt_pk_bf16(a - __uint_as_float(hi << 16), b - __uint_as_float(hi & 0xffff0000u));
+}
+// Eight floats -> 8 packed bf16 (hi) and, when lo != nullptr, the residuals.
+__device__ __forceinline__ void bf16_split8(const float (&v)[8], u32x4 &hi, u32x4 *lo) {
+    uint32_t h[4], l[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) bf16_split2(v[2 * i], v[2 * i + 1], h[i], l[i]);
+    hi = u32x4{h[0], h[1], h[2], h[3]};
+    if (lo) *lo = u32x4{l[0], l[1], l[2], l[3]};
+}
+__device__ __forceinline__ u32x4 bf16_round8(const float (&v)[8]) {
+    return u32x4{cvt_pk_bf16(v[0], v[1]), cvt_pk_bf16(v[2], v[3]), cvt_pk_bf16(v[4], v[5]), cvt_pk_bf16(v[6], v[7])};
 }
 
 __device__ __forceinline__ uint32_t pack2(uint32_t a, uint32_t b) { return a | (b << 16); }
