@@ -80,6 +80,17 @@ const char *ttm_status_string(int status);
 int ttm_version(void);
 
 /*
+ * Slab-kernel selection (process-wide), for tests and measurements that
+ * compare the two implementations of the fused mode-3/mode-2 step:
+ *   0 (default): the direct-to-LDS kernel wherever it applies (X already in
+ *      the operand format, 16-byte aligned rows, I3 a multiple of 256 bytes),
+ *      the register-staged kernel elsewhere;
+ *   1: the register-staged kernel everywhere.
+ * Returns TTM_ERR_INVALID_ARG for any other value.
+ */
+int ttm_set_slab_kernel(int mode);
+
+/*
  * Supported (x_dtype, f_dtype, y_dtype, math) combinations of ttm_chain:
  *   (F64,  F64, F64, F64)
  *   (F32,  F32, F32, F32)   (F32, F32, F32, BF16)   (F32, F32, F32, BF16X3)

@@ -38,6 +38,7 @@ PShape = ctypes.POINTER(Shape)
 SIGNATURES = {
     "ttm_status_string": (ctypes.c_char_p, [INT]),
     "ttm_version": (INT, []),
+    "ttm_set_slab_kernel": (INT, [INT]),
     "ttm_chain_supported": (INT, [INT, INT, INT, INT]),
     "ttm_chain_workspace_size": (SZ, [PShape, INT, INT]),
     "ttm_chain": (INT, [PShape, P, INT, P, P, P, INT, P, INT, INT, P, SZ, P]),

@@ -1,4 +1,5 @@
 // ttm_api.hip -- status strings, version, per-kernel timing registry.
+#include <atomic>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -52,6 +53,11 @@ void launch_end(hipStream_t s) {
     t_pending_start = nullptr;
 }
 
+namespace {
+std::atomic<int> g_slab_mode{0};
+}
+bool dma_disabled() { return g_slab_mode.load(std::memory_order_relaxed) == 1; }
+
 int device_cu_count() {
     static int cached[64] = {0};
     int dev = 0;
@@ -81,6 +87,12 @@ const char *ttm_status_string(int status) {
 }
 
 int ttm_version(void) { return 1 * 10000 + 0 * 100 + 0; }
+
+int ttm_set_slab_kernel(int mode) {
+    if (mode != 0 && mode != 1) return TTM_ERR_INVALID_ARG;
+    ttm::g_slab_mode.store(mode, std::memory_order_relaxed);
+    return TTM_OK;
+}
 
 int ttm_timing_enable(int on) {
     std::lock_guard<std::mutex> lk(ttm::g_mu);

@@ -390,6 +390,164 @@ __global__ void __launch_bounds__(SLAB_THREADS, 2) k_slab(const SlabArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// k_slab_dma: the same computation as k_slab for the common case where X is
+// already in the operand format (bf16 X with bf16/bf16x3 arithmetic, f32 X
+// with f32, f64 X with f64), rows are 16-byte aligned and I3 is a multiple of
+// the 256-byte chunk.  X goes from HBM straight into LDS (global_load_lds,
+// no register staging) in chunks of 128 rows x 256 bytes, double-buffered in
+// two LDS arrays so that the compiler's wait before each barrier covers
+// exactly the chunk about to be used.  Inside a chunk the 16-byte words of a
+// row are XOR-swizzled by (row & 7) so that the 16 rows of an operand
+// fragment fall in distinct LDS bank groups.  Rows past the end of a slab
+// range are read from a clamped (valid) row and their W rows zeroed before
+// the mode-2 step.
+// ---------------------------------------------------------------------------
+constexpr int DMA_ROWB = 256;                       // bytes of X per row per chunk
+constexpr int DMA_STAGE = SLAB_TM * DMA_ROWB;       // 32 KiB
+
+template <int MATH, int WC, int NBW, int JB>
+__global__ void __launch_bounds__(SLAB_THREADS, 2) k_slab_dma(const SlabArgs a) {
+    typedef MathTraits<MATH> TR;
+    typedef typename TR::lds_t LT;
+    typedef typename TR::accv_t accv_t;
+    typedef typename TR::acc_t acc_t;
+    typedef typename TR::fac_t FT;
+    constexpr int WR = 4 / WC, RW = SLAB_TM / WR, MB = RW / 16;
+    constexpr int VE = TR::VE, KG = TR::KG;
+    constexpr int KC = DMA_ROWB / int(sizeof(LT));      // k per chunk (4 k-groups)
+    static_assert(MB >= 2 && MB % 2 == 0, "row blocks per wave");
+
+    __shared__ __align__(1024) unsigned char st0[DMA_STAGE];
+    __shared__ __align__(1024) unsigned char st1[DMA_STAGE];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave / WC, wc = wave % WC;
+    const int l16 = lane & 15, g = lane >> 4;
+
+    const int64_t i1 = blockIdx.x / a.S;
+    const int s = int(blockIdx.x % a.S);
+    const int64_t row_begin = int64_t(s) * a.rows_per_split;
+    const int64_t row_end = a.I2 < row_begin + a.rows_per_split ? a.I2 : row_begin + a.rows_per_split;
+    const int64_t nrows = row_end > row_begin ? row_end - row_begin : 0;
+    const int64_t col0 = int64_t(blockIdx.y) * (WC * NBW * 16) + wc * NBW * 16;
+    const int jbase = int(blockIdx.z) * JB;
+
+    const LT *Xs = static_cast<const LT *>(a.X) + i1 * a.I2 * a.I3;
+    const int64_t nk = a.I3 / KC;
+    const int64_t ntiles = ceil_div(nrows, SLAB_TM);
+    const int64_t nq = ntiles * nk;
+    const FT *Ch = static_cast<const FT *>(a.Chi);
+    const FT *Cl = static_cast<const FT *>(a.Clo);
+
+    // DMA of chunk (t, kc) into one stage: wave w moves rows 32w .. 32w+31 as
+    // 8 blocks of 4 rows; lane l fills slot (row 4j + l/16, word l%16), which
+    // holds logical word (l%16) ^ (row & 7) of that row.
+    const int drow_in = lane >> 4, dpos = lane & 15;
+    auto dma = [&](unsigned char *stage, int64_t t, int64_t kc) {
+        const int64_t r0 = row_begin + t * SLAB_TM;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int row = wave * 32 + 4 * j + drow_in;
+            int64_t grow = r0 + row;
+            grow = grow < row_end ? grow : row_end - 1;
+            const int word = dpos ^ (row & 7);
+            const LT *src = Xs + grow * a.I3 + kc * KC + word * VE;
+            dma16_to_lds(src, stage + (wave * 32 + 4 * j) * DMA_ROWB);
+        }
+    };
+
+    accv_t vacc[JB][NBW];
+    accv_t wacc[MB][NBW];
+#pragma unroll
+    for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+        for (int nb = 0; nb < NBW; ++nb) vacc[jb][nb] = zero_accv<accv_t>();
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NBW; ++nb) wacc[mb][nb] = zero_accv<accv_t>();
+
+    // one chunk of matrix-core work from a stage
+    auto compute = [&](const unsigned char *stage, int64_t kc) {
+#pragma unroll
+        for (int kg = 0; kg < 4; ++kg) {
+            const int64_t k0 = kc * KC + kg * KG + g * VE;
+            V16 bh[NBW], bl[NBW];
+#pragma unroll
+            for (int nb = 0; nb < NBW; ++nb) {
+                const int64_t off = (col0 + nb * 16 + l16) * a.ldc + k0;
+                bh[nb] = ld16(Ch + off);
+                if constexpr (MATH == M_BF16X3) bl[nb] = ld16(Cl + off);
+            }
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) {
+                const int row = wr * RW + mb * 16 + l16;
+                const int word = (kg * 4 + g) ^ (row & 7);
+                V16 ah;
+                ah.u = *reinterpret_cast<const u32x4 *>(stage + row * DMA_ROWB + word * 16);
+#pragma unroll
+                for (int nb = 0; nb < NBW; ++nb) {
+                    mma_kgroup<MATH == M_BF16X3 ? M_BF16 : MATH>(wacc[mb][nb], ah, bh[nb]);
+                    if constexpr (MATH == M_BF16X3) mma_kgroup<M_BF16>(wacc[mb][nb], ah, bl[nb]);
+                }
+            }
+        }
+    };
+    // end of a 128-row tile: zero rows past the range, mode-2 step, reset W
+    auto tile_end = [&](int64_t t) {
+        const int64_t wrow0 = row_begin + t * SLAB_TM + wr * RW;
+        if (row_begin + (t + 1) * SLAB_TM > row_end) {
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const bool dead = wrow0 + mb * 16 + TR::acc_row(g, r) >= row_end;
+#pragma unroll
+                    for (int nb = 0; nb < NBW; ++nb)
+                        if (dead) wacc[mb][nb][r] = acc_t(0);
+                }
+        }
+        slab_mode2<MATH, MB, NBW, JB>(vacc, wacc, a, jbase, wrow0, l16, g);
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < NBW; ++nb) wacc[mb][nb] = zero_accv<accv_t>();
+    };
+
+    int64_t t = 0, kc = 0;       // chunk being computed
+    int64_t ft = 0, fkc = 0;     // chunk fetched next
+    auto next = [&](int64_t &tt, int64_t &kk) { if (++kk == nk) { kk = 0; ++tt; } };
+    if (nq > 0) {
+        dma(st0, ft, fkc);
+        next(ft, fkc);
+    }
+    for (int64_t q = 0; q < nq; q += 2) {
+        __syncthreads();                       // chunk q is in st0; st1 is free
+        if (q + 1 < nq) { dma(st1, ft, fkc); next(ft, fkc); }
+        compute(st0, kc);
+        if (kc == nk - 1) tile_end(t);
+        next(t, kc);
+        if (q + 1 >= nq) break;
+        __syncthreads();                       // chunk q+1 is in st1; st0 is free
+        if (q + 2 < nq) { dma(st0, ft, fkc); next(ft, fkc); }
+        compute(st1, kc);
+        if (kc == nk - 1) tile_end(t);
+        next(t, kc);
+    }
+
+    acc_t *Vp = static_cast<acc_t *>(a.V) + (i1 * a.P + int64_t(s) * WR + wr) * a.J2pad * a.J3pad;
+#pragma unroll
+    for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+        for (int nb = 0; nb < NBW; ++nb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t j2 = int64_t(jbase + jb) * 16 + TR::acc_row(g, r);
+                Vp[j2 * a.J3pad + col0 + nb * 16 + l16] = vacc[jb][nb][r];
+            }
+}
+
+// ---------------------------------------------------------------------------
 // Mode-1 contraction with partial sums:
 //   Y[j1, n] = sum_i1 A[j1, i1] * sum_p V[i1][p][n],   n = j2 * J3pad + j3.
 // A workgroup owns 64 columns n (wave w: columns 16w..16w+15) and every j1
@@ -696,8 +854,35 @@ static int launch_slab(const ChainPlan &p, const SlabArgs &a, hipStream_t st) {
     });
 }
 
+template <int MATH, int WC, int NBW, int JB>
+static int launch_slab_dma(const ChainPlan &p, const SlabArgs &a, hipStream_t st) {
+    dim3 grid(unsigned(a.I1 * a.S), unsigned(p.n_j3_tiles), unsigned(p.n_j2_tiles));
+    return launch("ttm_slab", st, [&] {
+        hipLaunchKernelGGL((k_slab_dma<MATH, WC, NBW, JB>), grid, dim3(SLAB_THREADS), 0, st, a);
+    });
+}
+
+// X already in operand format, 16-byte rows, whole 256-byte chunks per row
+template <int MATH, typename XT>
+static bool dma_applies(const SlabArgs &a) {
+    typedef typename MathTraits<MATH>::lds_t LT;
+    if constexpr (!std::is_same<XT, LT>::value) return false;
+    const int64_t kc = DMA_ROWB / int64_t(sizeof(LT));
+    return a.x_vec && (a.I3 % kc) == 0 && aligned(a.X, 16) && !dma_disabled();
+}
+
 template <int MATH, typename XT, int WC, int NBW>
 static int dispatch_slab_jb(const ChainPlan &p, const SlabArgs &a, hipStream_t st) {
+    if (dma_applies<MATH, XT>(a)) {
+        switch (p.JB) {
+            case 1: return launch_slab_dma<MATH, WC, NBW, 1>(p, a, st);
+            case 2: return launch_slab_dma<MATH, WC, NBW, 2>(p, a, st);
+            case 4: return launch_slab_dma<MATH, WC, NBW, 4>(p, a, st);
+            default:
+                if constexpr (MATH != M_F64) return launch_slab_dma<MATH, WC, NBW, 8>(p, a, st);
+                return TTM_ERR_UNSUPPORTED;
+        }
+    }
     switch (p.JB) {
         case 1: return launch_slab<MATH, XT, WC, NBW, 1>(p, a, st);
         case 2: return launch_slab<MATH, XT, WC, NBW, 2>(p, a, st);

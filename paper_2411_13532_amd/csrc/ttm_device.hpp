@@ -147,6 +147,16 @@ __device__ __forceinline__ void mma_kgroup<M_BF16>(f32x4 &acc, const V16 &a, con
     acc = mfma_bf16(a.u, b.u, acc);
 }
 
+// 16 bytes per lane from global memory straight into LDS (global_load_lds,
+// gfx950): lane l of the wave writes lds_wave_base + 16*l.  `lds_wave_base`
+// must be the same for the whole wave.  The builtin exists only in the device
+// compilation; the host pass sees an empty body.
+__device__ __forceinline__ void dma16_to_lds(const void *g, void *lds_wave_base) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    __builtin_amdgcn_global_load_lds(const_cast<void *>(g), lds_wave_base, 16, 0, 0);
+#endif
+}
+
 // Host/device rounding helpers for sizes.
 __host__ __device__ constexpr int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 __host__ __device__ constexpr int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }

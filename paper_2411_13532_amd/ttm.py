@@ -195,6 +195,11 @@ class BatchedPlan:
         return {"threads": out[0], "blocks_per_cu": out[1], "blocks": out[2]}
 
 
+def set_slab_kernel(mode: int) -> None:
+    """0: direct-to-LDS slab kernel where it applies (default); 1: register-staged everywhere."""
+    check(_lib.load().ttm_set_slab_kernel(int(mode)), "ttm_set_slab_kernel")
+
+
 def timing_enable(on: bool = True) -> None:
     check(_lib.load().ttm_timing_enable(1 if on else 0), "ttm_timing_enable")
 

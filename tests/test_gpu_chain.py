@@ -235,3 +235,44 @@ def test_c3_full_size(c3_inputs, math):
     err = pins.rel_fro(Y[:, :, cols].double().cpu().numpy(), ref)
     print(f"[c3 {math}] sampled rel err {err:.3e}", flush=True)
     assert err <= TOL[math]
+
+
+# ---------------------------------------------------------------------------
+# Both slab kernels (direct-to-LDS and register-staged) on shapes where the
+# direct-to-LDS one applies: whole 256-byte chunks along i3, ragged i2 ranges.
+# ---------------------------------------------------------------------------
+DMA_SHAPES = [((7, 300, 256), (20, 35, 70)), ((3, 129, 128), (16, 130, 128)), ((2, 513, 512), (64, 64, 64))]
+
+
+@pytest.fixture
+def slab_kernel_mode():
+    from paper_2411_13532_amd import set_slab_kernel
+    yield set_slab_kernel
+    set_slab_kernel(0)
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["dma", "staged"])
+@pytest.mark.parametrize("form", [("f64", None), ("f32", None), ("bf16", torch.bfloat16), ("bf16x3", torch.bfloat16)],
+                         ids=["f64", "f32", "bf16", "bf16x3"])
+@pytest.mark.parametrize("shape", DMA_SHAPES, ids=lambda s: f"I{s[0]}J{s[1]}")
+def test_slab_kernels_agree_with_oracle(shape, form, mode, slab_kernel_mode):
+    slab_kernel_mode(mode)
+    math, xdt = form
+    I, J = shape
+    p = workloads.random_problem(I, J, seed=sum(I) + sum(J))
+    check_vs_oracle(p, math, xdt)
+
+
+@pytest.mark.parametrize("form", [("f32", None), ("bf16x3", torch.bfloat16)], ids=["f32", "bf16x3"])
+def test_slab_kernels_identity_bitwise(form, slab_kernel_mode):
+    math, xdt = form
+    rng = np.random.default_rng(31)
+    I = (3, 200, 256)
+    X = torch.from_numpy(rng.standard_normal(I).astype(np.float32)).to(torch.bfloat16).float().numpy()
+    outs = []
+    for mode in (0, 1):
+        slab_kernel_mode(mode)
+        Y, Xd = run(X, *[np.eye(n) for n in I], math, xdt)
+        assert np.array_equal(Y, stored(Xd).astype(np.float64))
+        outs.append(Y)
+    assert np.array_equal(outs[0], outs[1])
