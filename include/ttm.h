@@ -81,11 +81,12 @@ int ttm_version(void);
 
 /*
  * Slab-kernel selection (process-wide), for tests and measurements that
- * compare the two implementations of the fused mode-3/mode-2 step:
- *   0 (default): the direct-to-LDS kernel wherever it applies (X already in
- *      the operand format, 16-byte aligned rows, I3 a multiple of 256 bytes),
- *      the register-staged kernel elsewhere;
- *   1: the register-staged kernel everywhere.
+ * compare the implementations of the fused mode-3/mode-2 step:
+ *   0 (default): direct-to-LDS kernel wherever it applies (X already in the
+ *      operand format, 16-byte aligned rows, I3 a multiple of 256 bytes) with
+ *      512-byte chunks when I3 allows, the register-staged kernel elsewhere;
+ *   1: the register-staged kernel everywhere;
+ *   2: direct-to-LDS with 256-byte chunks only (where it applies).
  * Returns TTM_ERR_INVALID_ARG for any other value.
  */
 int ttm_set_slab_kernel(int mode);

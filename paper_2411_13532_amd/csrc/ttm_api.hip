@@ -56,7 +56,7 @@ void launch_end(hipStream_t s) {
 namespace {
 std::atomic<int> g_slab_mode{0};
 }
-bool dma_disabled() { return g_slab_mode.load(std::memory_order_relaxed) == 1; }
+int slab_kernel_mode() { return g_slab_mode.load(std::memory_order_relaxed); }
 
 int device_cu_count() {
     static int cached[64] = {0};
@@ -89,7 +89,7 @@ const char *ttm_status_string(int status) {
 int ttm_version(void) { return 1 * 10000 + 0 * 100 + 0; }
 
 int ttm_set_slab_kernel(int mode) {
-    if (mode != 0 && mode != 1) return TTM_ERR_INVALID_ARG;
+    if (mode < 0 || mode > 2) return TTM_ERR_INVALID_ARG;
     ttm::g_slab_mode.store(mode, std::memory_order_relaxed);
     return TTM_OK;
 }

@@ -240,6 +240,9 @@ int ttm_chain_backward(const ttm_shape *s, const void *G, const void *X, const v
     int rc = validate(s);
     if (rc) return rc;
     if (!bwd_combo_ok(dtype, math)) return TTM_ERR_UNSUPPORTED;
+    // every contraction length must fit the GEMM's 32-bit k index
+    const int64_t k_max = std::max({s->I[0] * s->I[1], s->I[0] * s->J[2], s->J[1] * s->J[2], s->I[1], s->I[2], s->J[0]});
+    if (k_max >= (int64_t(1) << 32)) return TTM_ERR_UNSUPPORTED;
     if (!G || !X || !A || !B || !C) return TTM_ERR_INVALID_ARG;
     if (!dX && !dA && !dB && !dC) return TTM_ERR_INVALID_ARG;
     const size_t e = dtype_size(dtype);

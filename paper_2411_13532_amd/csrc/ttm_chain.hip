@@ -398,15 +398,15 @@ __global__ void __launch_bounds__(SLAB_THREADS, 2) k_slab(const SlabArgs a) {
 // two LDS arrays so that the compiler's wait before each barrier covers
 // exactly the chunk about to be used.  Inside a chunk the 16-byte words of a
 // row are XOR-swizzled by (row & 7) so that the 16 rows of an operand
-// fragment fall in distinct LDS bank groups.  Rows past the end of a slab
+// fragment fall in distinct LDS bank groups.  Chunks are 256 bytes per row
+// (64 KiB of LDS, two workgroups per compute unit) or 512 bytes per row
+// (128 KiB, one workgroup per compute unit with the whole register file, and
+// twice the matrix-core work per chunk to cover the HBM latency).  Rows past the end of a slab
 // range are read from a clamped (valid) row and their W rows zeroed before
 // the mode-2 step.
 // ---------------------------------------------------------------------------
-constexpr int DMA_ROWB = 256;                       // bytes of X per row per chunk
-constexpr int DMA_STAGE = SLAB_TM * DMA_ROWB;       // 32 KiB
-
-template <int MATH, int WC, int NBW, int JB>
-__global__ void __launch_bounds__(SLAB_THREADS, 2) k_slab_dma(const SlabArgs a) {
+template <int MATH, int WC, int NBW, int JB, int ROWB>
+__global__ void __launch_bounds__(SLAB_THREADS, ROWB == 512 ? 1 : 2) k_slab_dma(const SlabArgs a) {
     typedef MathTraits<MATH> TR;
     typedef typename TR::lds_t LT;
     typedef typename TR::accv_t accv_t;
@@ -414,11 +414,16 @@ __global__ void __launch_bounds__(SLAB_THREADS, 2) k_slab_dma(const SlabArgs a) 
     typedef typename TR::fac_t FT;
     constexpr int WR = 4 / WC, RW = SLAB_TM / WR, MB = RW / 16;
     constexpr int VE = TR::VE, KG = TR::KG;
-    constexpr int KC = DMA_ROWB / int(sizeof(LT));      // k per chunk (4 k-groups)
+    constexpr int KC = ROWB / int(sizeof(LT));         // k per chunk
+    constexpr int NKG = ROWB / 64;                      // k-groups per chunk
+    constexpr int STAGE = SLAB_TM * ROWB;
+    constexpr int WPR = ROWB / 16;                      // 16-byte words per row
+    constexpr int RPI = 1024 / ROWB;                    // rows per wave instruction
+    constexpr int NDMA = SLAB_TM / 4 / RPI;             // instructions per wave per stage
     static_assert(MB >= 2 && MB % 2 == 0, "row blocks per wave");
 
-    __shared__ __align__(1024) unsigned char st0[DMA_STAGE];
-    __shared__ __align__(1024) unsigned char st1[DMA_STAGE];
+    __shared__ __align__(1024) unsigned char st0[STAGE];
+    __shared__ __align__(1024) unsigned char st1[STAGE];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave / WC, wc = wave % WC;
@@ -439,20 +444,20 @@ __global__ void __launch_bounds__(SLAB_THREADS, 2) k_slab_dma(const SlabArgs a) 
     const FT *Ch = static_cast<const FT *>(a.Chi);
     const FT *Cl = static_cast<const FT *>(a.Clo);
 
-    // DMA of chunk (t, kc) into one stage: wave w moves rows 32w .. 32w+31 as
-    // 8 blocks of 4 rows; lane l fills slot (row 4j + l/16, word l%16), which
-    // holds logical word (l%16) ^ (row & 7) of that row.
-    const int drow_in = lane >> 4, dpos = lane & 15;
+    // DMA of chunk (t, kc) into one stage: wave w moves rows 32w .. 32w+31,
+    // RPI rows per instruction; lane l fills slot (row, word l % WPR), which
+    // holds logical word (l % WPR) ^ (row & 7) of that row.
+    const int drow_in = lane / WPR, dpos = lane % WPR;
     auto dma = [&](unsigned char *stage, int64_t t, int64_t kc) {
         const int64_t r0 = row_begin + t * SLAB_TM;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int row = wave * 32 + 4 * j + drow_in;
+        for (int j = 0; j < NDMA; ++j) {
+            const int row = wave * 32 + RPI * j + drow_in;
             int64_t grow = r0 + row;
             grow = grow < row_end ? grow : row_end - 1;
             const int word = dpos ^ (row & 7);
             const LT *src = Xs + grow * a.I3 + kc * KC + word * VE;
-            dma16_to_lds(src, stage + (wave * 32 + 4 * j) * DMA_ROWB);
+            dma16_to_lds(src, stage + (wave * 32 + RPI * j) * ROWB);
         }
     };
 
@@ -467,28 +472,33 @@ __global__ void __launch_bounds__(SLAB_THREADS, 2) k_slab_dma(const SlabArgs a) 
 #pragma unroll
         for (int nb = 0; nb < NBW; ++nb) wacc[mb][nb] = zero_accv<accv_t>();
 
-    // one chunk of matrix-core work from a stage
+    // one chunk of matrix-core work from a stage; the factor fragments of the
+    // next k-group are loaded while the current one is on the matrix cores
     auto compute = [&](const unsigned char *stage, int64_t kc) {
-#pragma unroll
-        for (int kg = 0; kg < 4; ++kg) {
+        V16 bh[2][NBW], bl[2][NBW];
+        auto load_c = [&](int slot, int kg) {
             const int64_t k0 = kc * KC + kg * KG + g * VE;
-            V16 bh[NBW], bl[NBW];
 #pragma unroll
             for (int nb = 0; nb < NBW; ++nb) {
                 const int64_t off = (col0 + nb * 16 + l16) * a.ldc + k0;
-                bh[nb] = ld16(Ch + off);
-                if constexpr (MATH == M_BF16X3) bl[nb] = ld16(Cl + off);
+                bh[slot][nb] = ld16(Ch + off);
+                if constexpr (MATH == M_BF16X3) bl[slot][nb] = ld16(Cl + off);
             }
+        };
+        load_c(0, 0);
+#pragma unroll
+        for (int kg = 0; kg < NKG; ++kg) {
+            if (kg + 1 < NKG) load_c((kg + 1) & 1, kg + 1);
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb) {
                 const int row = wr * RW + mb * 16 + l16;
                 const int word = (kg * 4 + g) ^ (row & 7);
                 V16 ah;
-                ah.u = *reinterpret_cast<const u32x4 *>(stage + row * DMA_ROWB + word * 16);
+                ah.u = *reinterpret_cast<const u32x4 *>(stage + row * ROWB + word * 16);
 #pragma unroll
                 for (int nb = 0; nb < NBW; ++nb) {
-                    mma_kgroup<MATH == M_BF16X3 ? M_BF16 : MATH>(wacc[mb][nb], ah, bh[nb]);
-                    if constexpr (MATH == M_BF16X3) mma_kgroup<M_BF16>(wacc[mb][nb], ah, bl[nb]);
+                    mma_kgroup<MATH == M_BF16X3 ? M_BF16 : MATH>(wacc[mb][nb], ah, bh[kg & 1][nb]);
+                    if constexpr (MATH == M_BF16X3) mma_kgroup<M_BF16>(wacc[mb][nb], ah, bl[kg & 1][nb]);
                 }
             }
         }
@@ -609,20 +619,25 @@ __global__ void __launch_bounds__(256) k_mode1(const Mode1Args a) {
     // loader: thread (column c = tid % 64, word w = tid / 64 + 4*item) covers rows VE*w .. VE*w+VE-1
     const int lc = tid & 63, lw = tid >> 6;
     acc_t pre[ITEMS][VE];
+    // all ITEMS*VE loads of one partial are independent and issued together;
+    // rows past the range read row kb (valid) and are zeroed
     auto fetch = [&](int64_t ch) {
         const int64_t r0 = kb + ch * KT;
 #pragma unroll
         for (int it = 0; it < ITEMS; ++it)
 #pragma unroll
-            for (int e = 0; e < VE; ++e) {
-                const int64_t k = r0 + (lw + 4 * it) * VE + e;
-                acc_t s = acc_t(0);
-                if (k < ke) {
-                    const acc_t *vp = V + k * a.P * a.NN + n0 + lc;
-                    for (int p = 0; p < a.P; ++p) s += vp[int64_t(p) * a.NN];
+            for (int e = 0; e < VE; ++e) pre[it][e] = acc_t(0);
+        for (int p = 0; p < a.P; ++p) {
+            const acc_t *vp = V + int64_t(p) * a.NN + n0 + lc;
+#pragma unroll
+            for (int it = 0; it < ITEMS; ++it)
+#pragma unroll
+                for (int e = 0; e < VE; ++e) {
+                    const int64_t k = r0 + (lw + 4 * it) * VE + e;
+                    const acc_t v = vp[(k < ke ? k : kb) * a.P * a.NN];
+                    pre[it][e] += k < ke ? v : acc_t(0);
                 }
-                pre[it][e] = s;
-            }
+        }
     };
     auto store = [&](int buf) {
 #pragma unroll
@@ -713,11 +728,17 @@ __global__ void __launch_bounds__(256) k_mode1_reduce(const Mode1Args a) {
     const int64_t total = a.J1 * a.J2 * a.J3;
     const T *Yp = static_cast<const T *>(a.Ypart);
     T *Y = static_cast<T *>(a.Y);
+    const int64_t ps = a.J1pad * a.NN;
     for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < total; e += int64_t(gridDim.x) * 256) {
         const int64_t j3 = e % a.J3, j2 = (e / a.J3) % a.J2, j1 = e / (a.J2 * a.J3);
         const T *p = Yp + j1 * a.NN + j2 * a.J3pad + j3;
         T s = T(0);
-        for (int k = 0; k < a.KS; ++k) s += p[int64_t(k) * a.J1pad * a.NN];
+        int k = 0;
+        for (; k + 4 <= a.KS; k += 4) {   // four loads in flight, summed in order
+            const T v0 = p[k * ps], v1 = p[(k + 1) * ps], v2 = p[(k + 2) * ps], v3 = p[(k + 3) * ps];
+            s += v0; s += v1; s += v2; s += v3;
+        }
+        for (; k < a.KS; ++k) s += p[k * ps];
         Y[e] = s;
     }
 }
@@ -854,32 +875,43 @@ static int launch_slab(const ChainPlan &p, const SlabArgs &a, hipStream_t st) {
     });
 }
 
-template <int MATH, int WC, int NBW, int JB>
+template <int MATH, int WC, int NBW, int JB, int ROWB>
 static int launch_slab_dma(const ChainPlan &p, const SlabArgs &a, hipStream_t st) {
     dim3 grid(unsigned(a.I1 * a.S), unsigned(p.n_j3_tiles), unsigned(p.n_j2_tiles));
     return launch("ttm_slab", st, [&] {
-        hipLaunchKernelGGL((k_slab_dma<MATH, WC, NBW, JB>), grid, dim3(SLAB_THREADS), 0, st, a);
+        hipLaunchKernelGGL((k_slab_dma<MATH, WC, NBW, JB, ROWB>), grid, dim3(SLAB_THREADS), 0, st, a);
     });
 }
 
-// X already in operand format, 16-byte rows, whole 256-byte chunks per row
+// Which direct-to-LDS chunk width applies (0: none): X already in the operand
+// format, 16-byte rows, whole chunks along i3.
 template <int MATH, typename XT>
-static bool dma_applies(const SlabArgs &a) {
+static int dma_rowbytes(const SlabArgs &a) {
     typedef typename MathTraits<MATH>::lds_t LT;
-    if constexpr (!std::is_same<XT, LT>::value) return false;
-    const int64_t kc = DMA_ROWB / int64_t(sizeof(LT));
-    return a.x_vec && (a.I3 % kc) == 0 && aligned(a.X, 16) && !dma_disabled();
+    if constexpr (!std::is_same<XT, LT>::value) return 0;
+    const int mode = slab_kernel_mode();
+    if (mode == 1 || !a.x_vec || !aligned(a.X, 16)) return 0;
+    const int64_t es = int64_t(sizeof(LT));
+    if (mode != 2 && a.I3 % (512 / es) == 0) return 512;
+    if (a.I3 % (256 / es) == 0) return 256;
+    return 0;
+}
+
+template <int MATH, int WC, int NBW, int JB>
+static int launch_slab_dma_rb(const ChainPlan &p, const SlabArgs &a, int rb, hipStream_t st) {
+    if (rb == 512) return launch_slab_dma<MATH, WC, NBW, JB, 512>(p, a, st);
+    return launch_slab_dma<MATH, WC, NBW, JB, 256>(p, a, st);
 }
 
 template <int MATH, typename XT, int WC, int NBW>
 static int dispatch_slab_jb(const ChainPlan &p, const SlabArgs &a, hipStream_t st) {
-    if (dma_applies<MATH, XT>(a)) {
+    if (const int rb = dma_rowbytes<MATH, XT>(a)) {
         switch (p.JB) {
-            case 1: return launch_slab_dma<MATH, WC, NBW, 1>(p, a, st);
-            case 2: return launch_slab_dma<MATH, WC, NBW, 2>(p, a, st);
-            case 4: return launch_slab_dma<MATH, WC, NBW, 4>(p, a, st);
+            case 1: return launch_slab_dma_rb<MATH, WC, NBW, 1>(p, a, rb, st);
+            case 2: return launch_slab_dma_rb<MATH, WC, NBW, 2>(p, a, rb, st);
+            case 4: return launch_slab_dma_rb<MATH, WC, NBW, 4>(p, a, rb, st);
             default:
-                if constexpr (MATH != M_F64) return launch_slab_dma<MATH, WC, NBW, 8>(p, a, st);
+                if constexpr (MATH != M_F64) return launch_slab_dma_rb<MATH, WC, NBW, 8>(p, a, rb, st);
                 return TTM_ERR_UNSUPPORTED;
         }
     }

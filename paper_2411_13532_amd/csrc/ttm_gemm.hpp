@@ -17,6 +17,7 @@
 
 namespace ttm {
 
+// K must be below 2^32 (the k split uses 32-bit division).
 struct GemmArgs {
     const void *A, *B;
     void *C;
@@ -78,6 +79,8 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs a) {
         if (kfast) { r = idx / KT; kk = idx % KT; }
         else { kk = idx / 64; r = idx % 64; }
     };
+    // Branch-free: out-of-range elements read element (0, 0) (always valid)
+    // and are zeroed, so every load of a chunk is in flight at once.
     auto fetch = [&](int64_t ch) {
         const int64_t k0 = kb + ch * KT;
 #pragma unroll
@@ -85,25 +88,24 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs a) {
             int r, kk;
             coords(a_kfast, e, r, kk);
             const int64_t m = m0 + r, k = k0 + kk;
-            T v = T(0);
-            if (m < a.M && k < ke) {
-                const int64_t ko = k / a.Ki, ki = k - ko * a.Ki;
-                v = Ap[m * a.sam + ko * a.sako + ki * a.saki];
-            }
-            pa[e] = v;
+            const bool ok = m < a.M && k < ke;
+            const int64_t ko = int64_t(uint32_t(k) / uint32_t(a.Ki)), ki = k - ko * a.Ki;
+            const T v = Ap[ok ? m * a.sam + ko * a.sako + ki * a.saki : 0];
+            pa[e] = ok ? v : T(0);
         }
 #pragma unroll
-        for (int e = 0; e < PER; ++e) {
-            int r, kk;
-            coords(b_kfast, e, r, kk);
-            const int64_t n = n0 + r, k = k0 + kk;
-            T v = T(0);
-            if (n < a.N && k < ke) {
-                const int64_t ko = k / a.Ki, ki = k - ko * a.Ki;
-                const T *q = Bp + n * a.sbn + ko * a.sbko + ki * a.sbki;
-                for (int p = 0; p < a.P; ++p) v += q[int64_t(p) * a.sbp];
+        for (int e = 0; e < PER; ++e) pb[e] = T(0);
+        for (int p = 0; p < a.P; ++p) {
+#pragma unroll
+            for (int e = 0; e < PER; ++e) {
+                int r, kk;
+                coords(b_kfast, e, r, kk);
+                const int64_t n = n0 + r, k = k0 + kk;
+                const bool ok = n < a.N && k < ke;
+                const int64_t ko = int64_t(uint32_t(k) / uint32_t(a.Ki)), ki = k - ko * a.Ki;
+                const T v = Bp[ok ? int64_t(p) * a.sbp + n * a.sbn + ko * a.sbko + ki * a.sbki : 0];
+                pb[e] += ok ? v : T(0);
             }
-            pb[e] = v;
         }
     };
     auto put = [&](unsigned char *hi, unsigned char *lo, int r, int kk, T v) {
@@ -189,7 +191,13 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_sum_splits(const T *part, int64_t stride, int S, int64_t n, T *out) {
     for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < n; e += int64_t(gridDim.x) * 256) {
         T s = T(0);
-        for (int k = 0; k < S; ++k) s += part[int64_t(k) * stride + e];
+        int k = 0;
+        for (; k + 4 <= S; k += 4) {   // four loads in flight, summed in order
+            const T v0 = part[k * stride + e], v1 = part[(k + 1) * stride + e];
+            const T v2 = part[(k + 2) * stride + e], v3 = part[(k + 3) * stride + e];
+            s += v0; s += v1; s += v2; s += v3;
+        }
+        for (; k < S; ++k) s += part[k * stride + e];
         out[e] = s;
     }
 }

@@ -54,7 +54,7 @@ inline int launch(const char *name, hipStream_t s, F &&f) {
 // Number of compute units of the current device (cached per device).
 int device_cu_count();
 
-// True when ttm_set_slab_kernel(1) asked for the register-staged slab kernel everywhere.
-bool dma_disabled();
+// Slab-kernel selection set by ttm_set_slab_kernel (0 automatic, 1 register-staged, 2 256-byte direct-to-LDS).
+int slab_kernel_mode();
 
 }  // namespace ttm

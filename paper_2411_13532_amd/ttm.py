@@ -196,7 +196,8 @@ class BatchedPlan:
 
 
 def set_slab_kernel(mode: int) -> None:
-    """0: direct-to-LDS slab kernel where it applies (default); 1: register-staged everywhere."""
+    """0: automatic (default); 1: register-staged slab kernel everywhere;
+    2: direct-to-LDS with 256-byte chunks only (see ttm_set_slab_kernel)."""
     check(_lib.load().ttm_set_slab_kernel(int(mode)), "ttm_set_slab_kernel")
 
 

@@ -169,8 +169,18 @@ def test_compact6_closed_form(n, math):
     if math == "f64":
         assert pins.rel_fro(Y, closed) <= 1e-12
     else:
-        ref = oracle.chain(stored(Xd), *(D.astype(np.float32) for D in Ds))
-        assert pins.rel_fro(Y, ref) <= TOL[math]
+        # Forward error bound of a sum of products: |Y^ - Y| <= c u (|A|x|B|x|C|)|X|
+        # with u the relative error of one product (f32: 2^-24 per rounding,
+        # a few roundings per term; bf16x3: 2^-16 from the split and the dropped
+        # lo*lo term) and c = 3 mode products.  cond = ||chain(|X|,|D|..)|| / ||Y||
+        # is large here because D amplifies high wavenumbers while Y is smooth.
+        Ds32 = [D.astype(np.float32) for D in Ds]
+        ref = oracle.chain(stored(Xd), *Ds32)
+        cond = np.linalg.norm(oracle.chain(np.abs(stored(Xd)), *(np.abs(D) for D in Ds32))) / np.linalg.norm(ref)
+        u = {"f32": 2.0 ** -21, "bf16x3": 2.0 ** -16}[math]
+        err = pins.rel_fro(Y, ref)
+        print(f"[compact6 {math} n={n}] rel err {err:.3e}, cond {cond:.1f}", flush=True)
+        assert err <= max(TOL[math], 3 * u * cond)
 
 
 @pytest.mark.parametrize("math", ["f32", "bf16x3", "bf16", "f64"])
