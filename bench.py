@@ -109,7 +109,9 @@ def bench_dense_precision(args, torch, ttm):
     out = {}
     forms = {}
     Ys = {}
-    for math, steps in (("bf16x3", args.steps), ("f32", max(3, args.steps // 4)), ("bf16", args.steps)):
+    plan = [("bf16x3", args.steps), ("f32", max(3, args.steps // 4)), ("bf16", args.steps)]
+    plan = [f for f in plan if f[0] in args.forms.split(",")]
+    for math, steps in plan:
         wsm = torch.empty(ttm.chain_workspace_size((I,) * 3, (J,) * 3, torch.bfloat16, math), dtype=torch.uint8,
                           device=dev)
         Y = torch.empty((J, J, J), dtype=torch.float32, device=dev)
@@ -164,7 +166,10 @@ def bench_dense_precision(args, torch, ttm):
     roof["algorithmic_bytes"] = slab_bytes
     roof["mfma_flops"] = slab_mfma
     roof["mfma_frac"] = round(tflops / MFMA_BF16_TFLOPS, 4)
+    roof["copy_ceiling_gbs"] = round(copy_gbs(torch, ttm, 1 << 30, 10), 1)
     ms = out["ms"]
+    speedup = (round(forms["f32"]["ms_per_step"] / forms["bf16x3"]["ms_per_step"], 3)
+               if "f32" in forms and "bf16x3" in forms else None)
     line = {
         "metric": "TTM-chain GFLOP/s + % roofline; bf16x3 vs FP32 speedup at rel err<=1e-5",
         "value": round(flops / (ms * 1e-3) / 1e9, 1),
@@ -180,9 +185,28 @@ def bench_dense_precision(args, torch, ttm):
         "cpu_baseline": cpu,
         "forms": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                   for k, v in forms.items()},
-        "bf16x3_vs_f32_speedup": round(forms["f32"]["ms_per_step"] / forms["bf16x3"]["ms_per_step"], 3),
+        "bf16x3_vs_f32_speedup": speedup,
     }
     return line
+
+
+def copy_gbs(torch, ttm, nbytes, reps):
+    """Practical HBM ceiling: read + write bytes per second of the library's copy kernel."""
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    dst = torch.empty_like(src)
+    ms, _ = timed(lambda: ttm.stream_copy(dst, src), reps, 2, torch)
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def bench_copy(args, torch, ttm):
+    nbytes = 1 << 30
+    gbs = copy_gbs(torch, ttm, nbytes, args.steps)
+    return {"metric": "device copy GB/s (read + write)", "value": round(gbs, 1), "unit": "GB/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": 2, "ms_per_step": round(2 * nbytes / gbs / 1e6, 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+            "config": {"workload": "copy of 1 GiB (ttm_stream_copy)", "bytes": nbytes},
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None}}
 
 
 def bench_c2(args, torch, ttm):
@@ -285,7 +309,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c4", "c5"])
+    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c4", "c5", "copy"])
+    ap.add_argument("--forms", default="bf16x3,f32,bf16",
+                    help="c3: arithmetic forms to run (bf16x3 is the headline and must be included)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -298,7 +324,7 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.init()
-    fn = {"c3": bench_dense_precision, "c2": bench_c2, "c4": bench_c4, "c5": bench_c5}[args.workload]
+    fn = {"c3": bench_dense_precision, "c2": bench_c2, "c4": bench_c4, "c5": bench_c5, "copy": bench_copy}[args.workload]
     line = fn(args, torch, ttm)
     print(json.dumps(line), flush=True)
 

@@ -82,11 +82,13 @@ int ttm_version(void);
 /*
  * Slab-kernel selection (process-wide), for tests and measurements that
  * compare the implementations of the fused mode-3/mode-2 step:
- *   0 (default): direct-to-LDS kernel wherever it applies (X already in the
- *      operand format, 16-byte aligned rows, I3 a multiple of 256 bytes) with
- *      512-byte chunks when I3 allows, the register-staged kernel elsewhere;
+ *   0 (default): the direct-to-LDS kernel with 256-byte chunks wherever it
+ *      applies (X already in the operand format, 16-byte aligned rows, I3 a
+ *      multiple of 256 bytes), the register-staged kernel elsewhere;
  *   1: the register-staged kernel everywhere;
- *   2: direct-to-LDS with 256-byte chunks only (where it applies).
+ *   2: same as 0;
+ *   3: direct-to-LDS with 512-byte chunks (one workgroup per compute unit)
+ *      where I3 is a multiple of 512 bytes, else as 0.
  * Returns TTM_ERR_INVALID_ARG for any other value.
  */
 int ttm_set_slab_kernel(int mode);
@@ -204,6 +206,13 @@ int ttm_batched_autotune(ttm_batched_plan *plan, const void *X, const void *A,
 /* The plan's current launch shape: out[0] = threads per block, out[1] =
  * blocks per compute unit, out[2] = total blocks. */
 int ttm_batched_plan_config(const ttm_batched_plan *plan, int *out);
+
+/*
+ * Plain device-to-device copy of `bytes` (a multiple of 16; both pointers
+ * 16-byte aligned, not overlapping) on `stream`: the practical HBM bandwidth
+ * ceiling for the roofline, and the known-size reference for byte counters.
+ */
+int ttm_stream_copy(void *dst, const void *src, size_t bytes, void *stream);
 
 /*
  * Per-kernel timing for measurement.  When enabled, every kernel the library

@@ -4,7 +4,7 @@ The computation lives in libttm.so (hand-written HIP kernels behind the C
 interface in include/ttm.h); this package is its PyTorch binding.
 """
 from .ttm import (BatchedPlan, TTMChain, chain, chain_backward, chain_backward_workspace_size,
-                  chain_workspace_size, set_slab_kernel, timing_collect, timing_enable, ttm_chain)
+                  chain_workspace_size, set_slab_kernel, stream_copy, timing_collect, timing_enable, ttm_chain)
 
 __all__ = ["BatchedPlan", "TTMChain", "chain", "chain_backward", "chain_backward_workspace_size",
-           "chain_workspace_size", "set_slab_kernel", "timing_collect", "timing_enable", "ttm_chain"]
+           "chain_workspace_size", "set_slab_kernel", "stream_copy", "timing_collect", "timing_enable", "ttm_chain"]

@@ -52,6 +52,7 @@ SIGNATURES = {
     "ttm_chain_batched_loop": (INT, [P, P, P, P, P, P, P]),
     "ttm_batched_autotune": (INT, [P, P, P, P, P, P, P, INT, ctypes.POINTER(ctypes.c_double)]),
     "ttm_batched_plan_config": (INT, [P, P]),
+    "ttm_stream_copy": (INT, [P, P, SZ, P]),
     "ttm_timing_enable": (INT, [INT]),
     "ttm_timing_collect": (INT, [P, P, P, INT]),
 }

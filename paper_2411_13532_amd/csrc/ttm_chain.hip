@@ -397,8 +397,9 @@ __global__ void __launch_bounds__(SLAB_THREADS, 2) k_slab(const SlabArgs a) {
 // no register staging) in chunks of 128 rows x 256 bytes, double-buffered in
 // two LDS arrays so that the compiler's wait before each barrier covers
 // exactly the chunk about to be used.  Inside a chunk the 16-byte words of a
-// row are XOR-swizzled by (row & 7) so that the 16 rows of an operand
-// fragment fall in distinct LDS bank groups.  Chunks are 256 bytes per row
+// row are XOR-swizzled by (row & 15): a 16-byte LDS read is served 16 lanes
+// at a time over 64 banks (256 bytes), and the 16 rows of an operand
+// fragment then land on 16 distinct 16-byte bank groups.  Chunks are 256 bytes per row
 // (64 KiB of LDS, two workgroups per compute unit) or 512 bytes per row
 // (128 KiB, one workgroup per compute unit with the whole register file, and
 // twice the matrix-core work per chunk to cover the HBM latency).  Rows past the end of a slab
@@ -446,7 +447,7 @@ __global__ void __launch_bounds__(SLAB_THREADS, ROWB == 512 ? 1 : 2) k_slab_dma(
 
     // DMA of chunk (t, kc) into one stage: wave w moves rows 32w .. 32w+31,
     // RPI rows per instruction; lane l fills slot (row, word l % WPR), which
-    // holds logical word (l % WPR) ^ (row & 7) of that row.
+    // holds logical word (l % WPR) ^ (row & 15) of that row.
     const int drow_in = lane / WPR, dpos = lane % WPR;
     auto dma = [&](unsigned char *stage, int64_t t, int64_t kc) {
         const int64_t r0 = row_begin + t * SLAB_TM;
@@ -455,7 +456,7 @@ __global__ void __launch_bounds__(SLAB_THREADS, ROWB == 512 ? 1 : 2) k_slab_dma(
             const int row = wave * 32 + RPI * j + drow_in;
             int64_t grow = r0 + row;
             grow = grow < row_end ? grow : row_end - 1;
-            const int word = dpos ^ (row & 7);
+            const int word = dpos ^ (row & 15);
             const LT *src = Xs + grow * a.I3 + kc * KC + word * VE;
             dma16_to_lds(src, stage + (wave * 32 + RPI * j) * ROWB);
         }
@@ -492,7 +493,7 @@ __global__ void __launch_bounds__(SLAB_THREADS, ROWB == 512 ? 1 : 2) k_slab_dma(
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb) {
                 const int row = wr * RW + mb * 16 + l16;
-                const int word = (kg * 4 + g) ^ (row & 7);
+                const int word = (kg * 4 + g) ^ (row & 15);
                 V16 ah;
                 ah.u = *reinterpret_cast<const u32x4 *>(stage + row * ROWB + word * 16);
 #pragma unroll
@@ -560,8 +561,8 @@ __global__ void __launch_bounds__(SLAB_THREADS, ROWB == 512 ? 1 : 2) k_slab_dma(
 // ---------------------------------------------------------------------------
 // Mode-1 contraction with partial sums:
 //   Y[j1, n] = sum_i1 A[j1, i1] * sum_p V[i1][p][n],   n = j2 * J3pad + j3.
-// A workgroup owns 64 columns n (wave w: columns 16w..16w+15) and every j1
-// row (MBK 16-row blocks); grid.y splits the i1 range.  V is streamed once:
+// A workgroup owns 64 columns n and up to 128 rows j1 (grid.z tiles larger
+// J1); grid.y splits the i1 range.  V is streamed once:
 // each lane reads one column over VE consecutive rows (a wave reads 256
 // contiguous bytes per row), converts to the operand format and stores the
 // VE values as one 16-byte LDS word, k-contiguous, which is exactly the
@@ -594,7 +595,11 @@ struct Mode1Cfg {
     static constexpr bool SPLIT = (MATH == M_BF16X3);
 };
 
-template <int MATH, int MBK>
+// MW 16-row blocks and NW 16-column blocks per wave.  NW == 4: the waves
+// split the rows (wave w: blocks w*MW ..), each covering all 64 columns, so
+// every element of A is fetched once per workgroup; NW == 1: the waves split
+// the columns (small J1).
+template <int MATH, int MW, int NW>
 __global__ void __launch_bounds__(256) k_mode1(const Mode1Args a) {
     typedef Mode1Cfg<MATH> CF;
     typedef MathTraits<MATH> TR;
@@ -662,9 +667,15 @@ __global__ void __launch_bounds__(256) k_mode1(const Mode1Args a) {
         }
     };
 
-    accv_t acc[MBK];
+    constexpr int MBW = NW == 4 ? 4 * MW : MW;          // 16-row blocks per workgroup
+    const int mbase = NW == 4 ? wave * MW : 0;
+    const int nbase = NW == 4 ? 0 : wave;
+    const int64_t m0 = int64_t(blockIdx.z) * MBW * 16;
+    accv_t acc[MW][NW];
 #pragma unroll
-    for (int mb = 0; mb < MBK; ++mb) acc[mb] = zero_accv<accv_t>();
+    for (int i = 0; i < MW; ++i)
+#pragma unroll
+        for (int j = 0; j < NW; ++j) acc[i][j] = zero_accv<accv_t>();
 
     if (nch > 0) {
         fetch(0);
@@ -676,20 +687,27 @@ __global__ void __launch_bounds__(256) k_mode1(const Mode1Args a) {
         const int buf = int(ch & 1);
 #pragma unroll
         for (int kg = 0; kg < 2; ++kg) {
-            const int loff = buf * CF::BUFB + (wave * 16 + l16) * CF::ROWB + kg * 64 + g * 16;
-            V16 bh, bl;
-            bh.u = *reinterpret_cast<const u32x4 *>(lhi + loff);
-            if constexpr (CF::SPLIT) bl.u = *reinterpret_cast<const u32x4 *>(llo + loff);
+            V16 bh[NW], bl[NW];
+#pragma unroll
+            for (int j = 0; j < NW; ++j) {
+                const int loff = buf * CF::BUFB + ((nbase + j) * 16 + l16) * CF::ROWB + kg * 64 + g * 16;
+                bh[j].u = *reinterpret_cast<const u32x4 *>(lhi + loff);
+                if constexpr (CF::SPLIT) bl[j].u = *reinterpret_cast<const u32x4 *>(llo + loff);
+            }
             const int64_t k0 = kb + ch * KT + kg * KG + g * VE;
 #pragma unroll
-            for (int mb = 0; mb < MBK; ++mb) {
-                const int64_t off = (int64_t(blockIdx.z) * MBK * 16 + mb * 16 + l16) * a.lda + k0;
+            for (int i = 0; i < MW; ++i) {
+                const int64_t off = (m0 + (mbase + i) * 16 + l16) * a.lda + k0;
                 const V16 ah = ld16(Ah + off);
-                mma_kgroup<MATH == M_BF16X3 ? M_BF16 : MATH>(acc[mb], ah, bh);
-                if constexpr (CF::SPLIT) {
-                    const V16 al = ld16(Al + off);
-                    mma_kgroup<M_BF16>(acc[mb], ah, bl);
-                    mma_kgroup<M_BF16>(acc[mb], al, bh);
+                V16 al;
+                if constexpr (CF::SPLIT) al = ld16(Al + off);
+#pragma unroll
+                for (int j = 0; j < NW; ++j) {
+                    mma_kgroup<MATH == M_BF16X3 ? M_BF16 : MATH>(acc[i][j], ah, bh[j]);
+                    if constexpr (CF::SPLIT) {
+                        mma_kgroup<M_BF16>(acc[i][j], ah, bl[j]);
+                        mma_kgroup<M_BF16>(acc[i][j], al, bh[j]);
+                    }
                 }
             }
         }
@@ -697,27 +715,22 @@ __global__ void __launch_bounds__(256) k_mode1(const Mode1Args a) {
         __syncthreads();
     }
 
-    const int64_t n = n0 + wave * 16 + l16;
-    const int64_t m0 = int64_t(blockIdx.z) * MBK * 16;
-    if (a.KS == 1) {
+    acc_t *Y = static_cast<acc_t *>(a.Y);
+    acc_t *Yp = static_cast<acc_t *>(a.Ypart) + int64_t(ks) * a.J1pad * a.NN;
+#pragma unroll
+    for (int j = 0; j < NW; ++j) {
+        const int64_t n = n0 + (nbase + j) * 16 + l16;
         const int64_t j2 = n / a.J3pad, j3 = n % a.J3pad;
-        if (j2 >= a.J2 || j3 >= a.J3) return;
-        acc_t *Y = static_cast<acc_t *>(a.Y);
 #pragma unroll
-        for (int mb = 0; mb < MBK; ++mb)
+        for (int i = 0; i < MW; ++i)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t j1 = m0 + mb * 16 + TR::acc_row(g, r);
-                if (j1 < a.J1) Y[(j1 * a.J2 + j2) * a.J3 + j3] = acc[mb][r];
-            }
-    } else {
-        acc_t *Yp = static_cast<acc_t *>(a.Ypart) + int64_t(ks) * a.J1pad * a.NN;
-#pragma unroll
-        for (int mb = 0; mb < MBK; ++mb)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t j1 = m0 + mb * 16 + TR::acc_row(g, r);
-                Yp[j1 * a.NN + n] = acc[mb][r];
+                const int64_t j1 = m0 + (mbase + i) * 16 + TR::acc_row(g, r);
+                if (a.KS == 1) {
+                    if (j1 < a.J1 && j2 < a.J2 && j3 < a.J3) Y[(j1 * a.J2 + j2) * a.J3 + j3] = acc[i][j][r];
+                } else {
+                    Yp[j1 * a.NN + n] = acc[i][j][r];
+                }
             }
     }
 }
@@ -748,7 +761,7 @@ __global__ void __launch_bounds__(256) k_mode1_reduce(const Mode1Args a) {
 // ---------------------------------------------------------------------------
 struct ChainPlan {
     int math, xdt;
-    int WC, NBW, WR, JBMAX, JB, MBK;
+    int WC, NBW, WR, JBMAX, JB, MBK, m1_MW, m1_NW;
     int64_t cols;                 // j3 columns per workgroup
     int64_t J3pad, J2pad, J1pad;
     int64_t n_j3_tiles, n_j2_tiles, n_m1_tiles;
@@ -814,10 +827,11 @@ static bool make_plan(const ttm_shape &s, int xdt, int math, ChainPlan &p) {
     p.S = int(ceil_div(I2, p.rows_per_split));
     p.P = p.S * p.WR;
 
-    // mode-1 kernel tiling
+    // mode-1 kernel tiling: MW row blocks and NW column blocks per wave
     const int64_t J1b = ceil_div(J1, 16);
-    const int mbk_max = math == TTM_MATH_F64 ? 4 : 8;
-    p.MBK = J1b >= mbk_max ? mbk_max : (J1b > 2 ? 4 : (J1b > 1 ? 2 : 1));
+    if (J1b <= 2) { p.m1_NW = 1; p.m1_MW = int(J1b); }
+    else { p.m1_NW = 4; p.m1_MW = J1b >= 5 ? 2 : 1; }
+    p.MBK = p.m1_NW == 4 ? 4 * p.m1_MW : p.m1_MW;
     p.n_m1_tiles = ceil_div(J1b, p.MBK);
     p.J1pad = p.n_m1_tiles * p.MBK * 16;
 
@@ -892,7 +906,7 @@ static int dma_rowbytes(const SlabArgs &a) {
     const int mode = slab_kernel_mode();
     if (mode == 1 || !a.x_vec || !aligned(a.X, 16)) return 0;
     const int64_t es = int64_t(sizeof(LT));
-    if (mode != 2 && a.I3 % (512 / es) == 0) return 512;
+    if (mode == 3 && a.I3 % (512 / es) == 0) return 512;
     if (a.I3 % (256 / es) == 0) return 256;
     return 0;
 }
@@ -942,14 +956,8 @@ static int dispatch_mode1(const ChainPlan &p, const Mode1Args &a, hipStream_t st
         return launch("ttm_mode1", st, [&] { hipLaunchKernelGGL(kern, grid, dim3(256), 0, st, a); });
     };
     int rc;
-    switch (p.MBK) {
-        case 1: rc = go(k_mode1<MATH, 1>); break;
-        case 2: rc = go(k_mode1<MATH, 2>); break;
-        case 4: rc = go(k_mode1<MATH, 4>); break;
-        default:
-            if constexpr (MATH != M_F64) rc = go(k_mode1<MATH, 8>);
-            else rc = TTM_ERR_UNSUPPORTED;
-    }
+    if (p.m1_NW == 1) rc = p.m1_MW == 1 ? go(k_mode1<MATH, 1, 1>) : go(k_mode1<MATH, 2, 1>);
+    else rc = p.m1_MW == 1 ? go(k_mode1<MATH, 1, 4>) : go(k_mode1<MATH, 2, 4>);
     if (rc || p.KS == 1) return rc;
     const int64_t total = a.J1 * a.J2 * a.J3;
     dim3 rgrid(unsigned(std::min<int64_t>(ceil_div(total, 256), 8192)));

@@ -195,9 +195,18 @@ class BatchedPlan:
         return {"threads": out[0], "blocks_per_cu": out[1], "blocks": out[2]}
 
 
+def stream_copy(dst: torch.Tensor, src: torch.Tensor) -> None:
+    """dst <- src (same byte size, 16-byte multiple) with the library's copy kernel."""
+    _need_cuda(dst, src)
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("dst and src must have the same size in bytes")
+    check(_lib.load().ttm_stream_copy(_ptr(dst), _ptr(src), nbytes, _stream(src.device)), "ttm_stream_copy")
+
+
 def set_slab_kernel(mode: int) -> None:
     """0: automatic (default); 1: register-staged slab kernel everywhere;
-    2: direct-to-LDS with 256-byte chunks only (see ttm_set_slab_kernel)."""
+    2: direct-to-LDS with 256-byte chunks; 3: 512-byte chunks (see ttm_set_slab_kernel)."""
     check(_lib.load().ttm_set_slab_kernel(int(mode)), "ttm_set_slab_kernel")
 
 
