@@ -82,13 +82,14 @@ int ttm_version(void);
 /*
  * Slab-kernel selection (process-wide), for tests and measurements that
  * compare the implementations of the fused mode-3/mode-2 step:
- *   0 (default): the direct-to-LDS kernel with 256-byte chunks wherever it
- *      applies (X already in the operand format, 16-byte aligned rows, I3 a
- *      multiple of 256 bytes), the register-staged kernel elsewhere;
+ *   0 (default): where X is already in the operand format with 16-byte
+ *      aligned rows and I3 a multiple of 256 bytes, the direct-to-LDS kernel
+ *      with a dedicated copy wave (three stages, two chunks in flight);
+ *      the register-staged kernel elsewhere;
  *   1: the register-staged kernel everywhere;
- *   2: same as 0;
- *   3: direct-to-LDS with 512-byte chunks (one workgroup per compute unit)
- *      where I3 is a multiple of 512 bytes, else as 0.
+ *   2: direct-to-LDS, 256-byte chunks, two stages, no copy wave;
+ *   3: direct-to-LDS, 512-byte chunks, two stages, one workgroup per
+ *      compute unit (where I3 is a multiple of 512 bytes, else as 0).
  * Returns TTM_ERR_INVALID_ARG for any other value.
  */
 int ttm_set_slab_kernel(int mode);

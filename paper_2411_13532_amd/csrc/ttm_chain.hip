@@ -559,6 +559,176 @@ __global__ void __launch_bounds__(SLAB_THREADS, ROWB == 512 ? 1 : 2) k_slab_dma(
 }
 
 // ---------------------------------------------------------------------------
+// k_slab_ws: the direct-to-LDS slab kernel with a dedicated copy wave.
+//
+// A vector-memory wait on gfx9 is in order: waiting for any load also waits
+// for every older one.  When the compute waves both start the X copy of the
+// next chunk and load their factor fragments, each factor-fragment wait also
+// waits for that copy, which exposes the HBM latency once per chunk.  Here a
+// fifth wave issues all X copies (three LDS stages, two chunks in flight) and
+// waits only for them; the four compute waves issue only the short factor
+// loads.  One barrier per chunk: before it the copy wave waits until chunk q
+// has landed (at most the 32 copies of chunk q+1 still in flight); after it
+// the copy wave starts chunk q+2 into the stage chunk q-1 used, and the
+// compute waves work on chunk q.  Every wave executes the same number of
+// barriers, and the loop bounds are uniform, so the grid always drains.
+// ---------------------------------------------------------------------------
+constexpr int WS_ROWB = 256;
+constexpr int WS_NS = 3;
+constexpr int WS_STAGE = SLAB_TM * WS_ROWB;          // 32 KiB
+constexpr int WS_THREADS = SLAB_THREADS + 64;
+constexpr int WS_NDMA = WS_STAGE / 1024;             // copy instructions per stage (one wave)
+
+// s_waitcnt with only the vector-memory count limited (gfx9 encoding:
+// vmcnt bits [3:0] and [15:14], expcnt and lgkmcnt at their maxima).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 0xf) | ((N >> 4) << 14) | (0x7 << 4) | (0xf << 8));
+}
+
+template <int MATH, int WC, int NBW, int JB>
+__global__ void __launch_bounds__(WS_THREADS, 2) k_slab_ws(const SlabArgs a) {
+    typedef MathTraits<MATH> TR;
+    typedef typename TR::lds_t LT;
+    typedef typename TR::accv_t accv_t;
+    typedef typename TR::acc_t acc_t;
+    typedef typename TR::fac_t FT;
+    constexpr int WR = 4 / WC, RW = SLAB_TM / WR, MB = RW / 16;
+    constexpr int VE = TR::VE, KG = TR::KG;
+    constexpr int KC = WS_ROWB / int(sizeof(LT));
+    constexpr int NKG = WS_ROWB / 64;
+    static_assert(MB >= 2 && MB % 2 == 0, "row blocks per wave");
+
+    __shared__ __align__(1024) unsigned char stages[WS_NS * WS_STAGE];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t i1 = blockIdx.x / a.S;
+    const int s = int(blockIdx.x % a.S);
+    const int64_t row_begin = int64_t(s) * a.rows_per_split;
+    const int64_t row_end = a.I2 < row_begin + a.rows_per_split ? a.I2 : row_begin + a.rows_per_split;
+    const int64_t nrows = row_end > row_begin ? row_end - row_begin : 0;
+    const int64_t nk = a.I3 / KC;
+    const int64_t ntiles = ceil_div(nrows, SLAB_TM);
+    const int64_t nq = ntiles * nk;
+    const LT *Xs = static_cast<const LT *>(a.X) + i1 * a.I2 * a.I3;
+
+    if (wave == 4) {
+        // ---- copy wave ----
+        const int drow = lane >> 4, dpos = lane & 15;
+        auto dma = [&](int64_t q) {
+            const int64_t t = q / nk, kc = q - t * nk;
+            unsigned char *stage = stages + int(q % WS_NS) * WS_STAGE;
+            const int64_t r0 = row_begin + t * SLAB_TM;
+#pragma unroll 8
+            for (int j = 0; j < WS_NDMA; ++j) {
+                const int row = 4 * j + drow;
+                int64_t grow = r0 + row;
+                grow = grow < row_end ? grow : row_end - 1;
+                const int word = dpos ^ (row & 15);
+                dma16_to_lds(Xs + grow * a.I3 + kc * KC + word * VE, stage + 4 * j * WS_ROWB);
+            }
+        };
+        if (nq > 0) dma(0);
+        if (nq > 1) dma(1);
+        for (int64_t q = 0; q < nq; ++q) {
+            if (q + 1 < nq) wait_vmcnt<WS_NDMA>();   // chunk q landed; chunk q+1 may be in flight
+            else wait_vmcnt<0>();
+            __builtin_amdgcn_s_barrier();
+            if (q + 2 < nq) dma(q + 2);
+        }
+        return;
+    }
+
+    // ---- compute waves ----
+    const int wr = wave / WC, wc = wave % WC;
+    const int l16 = lane & 15, g = lane >> 4;
+    const int64_t col0 = int64_t(blockIdx.y) * (WC * NBW * 16) + wc * NBW * 16;
+    const int jbase = int(blockIdx.z) * JB;
+    const FT *Ch = static_cast<const FT *>(a.Chi);
+    const FT *Cl = static_cast<const FT *>(a.Clo);
+
+    accv_t vacc[JB][NBW];
+    accv_t wacc[MB][NBW];
+#pragma unroll
+    for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+        for (int nb = 0; nb < NBW; ++nb) vacc[jb][nb] = zero_accv<accv_t>();
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NBW; ++nb) wacc[mb][nb] = zero_accv<accv_t>();
+
+    int64_t t = 0, kc = 0;
+    for (int64_t q = 0; q < nq; ++q) {
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        const unsigned char *stage = stages + int(q % WS_NS) * WS_STAGE;
+        V16 bh[2][NBW], bl[2][NBW];
+        auto load_c = [&](int slot, int kg) {
+            const int64_t k0 = kc * KC + kg * KG + g * VE;
+#pragma unroll
+            for (int nb = 0; nb < NBW; ++nb) {
+                const int64_t off = (col0 + nb * 16 + l16) * a.ldc + k0;
+                bh[slot][nb] = ld16(Ch + off);
+                if constexpr (MATH == M_BF16X3) bl[slot][nb] = ld16(Cl + off);
+            }
+        };
+        load_c(0, 0);
+#pragma unroll
+        for (int kg = 0; kg < NKG; ++kg) {
+            if (kg + 1 < NKG) load_c((kg + 1) & 1, kg + 1);
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) {
+                const int row = wr * RW + mb * 16 + l16;
+                const int word = (kg * 4 + g) ^ (row & 15);
+                V16 ah;
+                ah.u = *reinterpret_cast<const u32x4 *>(stage + row * WS_ROWB + word * 16);
+#pragma unroll
+                for (int nb = 0; nb < NBW; ++nb) {
+                    mma_kgroup<MATH == M_BF16X3 ? M_BF16 : MATH>(wacc[mb][nb], ah, bh[kg & 1][nb]);
+                    if constexpr (MATH == M_BF16X3) mma_kgroup<M_BF16>(wacc[mb][nb], ah, bl[kg & 1][nb]);
+                }
+            }
+        }
+        if (kc == nk - 1) {
+            const int64_t wrow0 = row_begin + t * SLAB_TM + wr * RW;
+            if (row_begin + (t + 1) * SLAB_TM > row_end) {
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const bool dead = wrow0 + mb * 16 + TR::acc_row(g, r) >= row_end;
+#pragma unroll
+                        for (int nb = 0; nb < NBW; ++nb)
+                            if (dead) wacc[mb][nb][r] = acc_t(0);
+                    }
+            }
+            slab_mode2<MATH, MB, NBW, JB>(vacc, wacc, a, jbase, wrow0, l16, g);
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                for (int nb = 0; nb < NBW; ++nb) wacc[mb][nb] = zero_accv<accv_t>();
+            kc = 0;
+            ++t;
+        } else {
+            ++kc;
+        }
+    }
+
+    acc_t *Vp = static_cast<acc_t *>(a.V) + (i1 * a.P + int64_t(s) * WR + wr) * a.J2pad * a.J3pad;
+#pragma unroll
+    for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+        for (int nb = 0; nb < NBW; ++nb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t j2 = int64_t(jbase + jb) * 16 + TR::acc_row(g, r);
+                Vp[j2 * a.J3pad + col0 + nb * 16 + l16] = vacc[jb][nb][r];
+            }
+}
+
+// ---------------------------------------------------------------------------
 // Mode-1 contraction with partial sums:
 //   Y[j1, n] = sum_i1 A[j1, i1] * sum_p V[i1][p][n],   n = j2 * J3pad + j3.
 // A workgroup owns 64 columns n and up to 128 rows j1 (grid.z tiles larger
@@ -914,7 +1084,11 @@ static int dma_rowbytes(const SlabArgs &a) {
 template <int MATH, int WC, int NBW, int JB>
 static int launch_slab_dma_rb(const ChainPlan &p, const SlabArgs &a, int rb, hipStream_t st) {
     if (rb == 512) return launch_slab_dma<MATH, WC, NBW, JB, 512>(p, a, st);
-    return launch_slab_dma<MATH, WC, NBW, JB, 256>(p, a, st);
+    if (rb == 256 && slab_kernel_mode() == 2) return launch_slab_dma<MATH, WC, NBW, JB, 256>(p, a, st);
+    dim3 grid(unsigned(a.I1 * a.S), unsigned(p.n_j3_tiles), unsigned(p.n_j2_tiles));
+    return launch("ttm_slab", st, [&] {
+        hipLaunchKernelGGL((k_slab_ws<MATH, WC, NBW, JB>), grid, dim3(WS_THREADS), 0, st, a);
+    });
 }
 
 template <int MATH, typename XT, int WC, int NBW>
