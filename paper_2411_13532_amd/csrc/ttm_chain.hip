@@ -587,17 +587,46 @@ __device__ __forceinline__ void wait_vmcnt() {
     __builtin_amdgcn_s_waitcnt((N & 0xf) | ((N >> 4) << 14) | (0x7 << 4) | (0xf << 8));
 }
 
-template <int MATH, int WC, int NBW, int JB>
+// Operand fragment of X for one k-group from a swizzled stage row (16-byte
+// words w stored at w ^ (row & 15)).  X keeps its storage type in LDS; a
+// bf16 X feeding float products is widened here, a float X feeding bf16
+// products is rounded (and split for bf16x3) here.
+template <int MATH, typename XT>
+__device__ __forceinline__ void ws_afrag(const unsigned char *rowp, int row, int kg, int g, V16 &ah, V16 &al) {
+    constexpr int KG = MathTraits<MATH>::KG;
+    const int sw = row & 15;
+    if constexpr (std::is_same<XT, typename MathTraits<MATH>::lds_t>::value) {
+        ah.u = *reinterpret_cast<const u32x4 *>(rowp + ((kg * 4 + g) ^ sw) * 16);
+    } else if constexpr (MATH == M_F32) {            // bf16 X: 4 values = 8 bytes
+        const int byte = (kg * KG + 4 * g) * 2;
+        const u32x2 h = *reinterpret_cast<const u32x2 *>(rowp + (((byte >> 4) ^ sw) << 4) + (byte & 15));
+        ah.f[0] = __uint_as_float(h[0] << 16);
+        ah.f[1] = __uint_as_float(h[0] & 0xffff0000u);
+        ah.f[2] = __uint_as_float(h[1] << 16);
+        ah.f[3] = __uint_as_float(h[1] & 0xffff0000u);
+    } else {                                          // float X, bf16 products: 8 values = 32 bytes
+        const int w = (kg * KG + 8 * g) * 4 / 16;
+        V16 lo4, hi4;
+        lo4.u = *reinterpret_cast<const u32x4 *>(rowp + ((w ^ sw) << 4));
+        hi4.u = *reinterpret_cast<const u32x4 *>(rowp + (((w + 1) ^ sw) << 4));
+        const float v[8] = {lo4.f[0], lo4.f[1], lo4.f[2], lo4.f[3], hi4.f[0], hi4.f[1], hi4.f[2], hi4.f[3]};
+        if constexpr (MATH == M_BF16X3) bf16_split8(v, ah.u, &al.u);
+        else ah.u = bf16_round8(v);
+    }
+}
+
+template <int MATH, typename XT, int WC, int NBW, int JB>
 __global__ void __launch_bounds__(WS_THREADS, 2) k_slab_ws(const SlabArgs a) {
     typedef MathTraits<MATH> TR;
-    typedef typename TR::lds_t LT;
     typedef typename TR::accv_t accv_t;
     typedef typename TR::acc_t acc_t;
     typedef typename TR::fac_t FT;
     constexpr int WR = 4 / WC, RW = SLAB_TM / WR, MB = RW / 16;
     constexpr int VE = TR::VE, KG = TR::KG;
-    constexpr int KC = WS_ROWB / int(sizeof(LT));
-    constexpr int NKG = WS_ROWB / 64;
+    constexpr int XVE = 16 / int(sizeof(XT));        // X values per 16-byte word
+    constexpr int KC = WS_ROWB / int(sizeof(XT));    // k per chunk
+    constexpr int NKG = KC / KG;                     // k-groups per chunk
+    constexpr bool XLO = (MATH == M_BF16X3) && std::is_same<XT, float>::value;
     static_assert(MB >= 2 && MB % 2 == 0, "row blocks per wave");
 
     __shared__ __align__(1024) unsigned char stages[WS_NS * WS_STAGE];
@@ -611,7 +640,7 @@ __global__ void __launch_bounds__(WS_THREADS, 2) k_slab_ws(const SlabArgs a) {
     const int64_t nk = a.I3 / KC;
     const int64_t ntiles = ceil_div(nrows, SLAB_TM);
     const int64_t nq = ntiles * nk;
-    const LT *Xs = static_cast<const LT *>(a.X) + i1 * a.I2 * a.I3;
+    const XT *Xs = static_cast<const XT *>(a.X) + i1 * a.I2 * a.I3;
 
     if (wave == 4) {
         // ---- copy wave ----
@@ -626,7 +655,7 @@ __global__ void __launch_bounds__(WS_THREADS, 2) k_slab_ws(const SlabArgs a) {
                 int64_t grow = r0 + row;
                 grow = grow < row_end ? grow : row_end - 1;
                 const int word = dpos ^ (row & 15);
-                dma16_to_lds(Xs + grow * a.I3 + kc * KC + word * VE, stage + 4 * j * WS_ROWB);
+                dma16_to_lds(Xs + grow * a.I3 + kc * KC + word * XVE, stage + 4 * j * WS_ROWB);
             }
         };
         if (nq > 0) dma(0);
@@ -681,13 +710,13 @@ __global__ void __launch_bounds__(WS_THREADS, 2) k_slab_ws(const SlabArgs a) {
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb) {
                 const int row = wr * RW + mb * 16 + l16;
-                const int word = (kg * 4 + g) ^ (row & 15);
-                V16 ah;
-                ah.u = *reinterpret_cast<const u32x4 *>(stage + row * WS_ROWB + word * 16);
+                V16 ah, al;
+                ws_afrag<MATH, XT>(stage + row * WS_ROWB, row, kg, g, ah, al);
 #pragma unroll
                 for (int nb = 0; nb < NBW; ++nb) {
                     mma_kgroup<MATH == M_BF16X3 ? M_BF16 : MATH>(wacc[mb][nb], ah, bh[kg & 1][nb]);
                     if constexpr (MATH == M_BF16X3) mma_kgroup<M_BF16>(wacc[mb][nb], ah, bl[kg & 1][nb]);
+                    if constexpr (XLO) mma_kgroup<M_BF16>(wacc[mb][nb], al, bh[kg & 1][nb]);
                 }
             }
         }
@@ -1067,27 +1096,34 @@ static int launch_slab_dma(const ChainPlan &p, const SlabArgs &a, hipStream_t st
     });
 }
 
-// Which direct-to-LDS chunk width applies (0: none): X already in the operand
-// format, 16-byte rows, whole chunks along i3.
+// Which direct-to-LDS variant applies (0: none): 16-byte aligned rows and
+// whole chunks along i3.  The two-stage kernels (modes 2 and 3) need X
+// already in the operand format; the copy-wave kernel widens or rounds X
+// while reading its fragments, so it takes any storage type.
 template <int MATH, typename XT>
 static int dma_rowbytes(const SlabArgs &a) {
     typedef typename MathTraits<MATH>::lds_t LT;
-    if constexpr (!std::is_same<XT, LT>::value) return 0;
     const int mode = slab_kernel_mode();
     if (mode == 1 || !a.x_vec || !aligned(a.X, 16)) return 0;
-    const int64_t es = int64_t(sizeof(LT));
-    if (mode == 3 && a.I3 % (512 / es) == 0) return 512;
-    if (a.I3 % (256 / es) == 0) return 256;
-    return 0;
+    const int64_t es = int64_t(sizeof(XT));
+    if (mode == 2 || mode == 3) {
+        if constexpr (!std::is_same<XT, LT>::value) return 0;
+        if (mode == 3 && a.I3 % (512 / es) == 0) return 512;
+        return a.I3 % (256 / es) == 0 ? 256 : 0;
+    }
+    return a.I3 % (256 / es) == 0 ? 1 : 0;   // copy-wave kernel
 }
 
-template <int MATH, int WC, int NBW, int JB>
+template <int MATH, typename XT, int WC, int NBW, int JB>
 static int launch_slab_dma_rb(const ChainPlan &p, const SlabArgs &a, int rb, hipStream_t st) {
-    if (rb == 512) return launch_slab_dma<MATH, WC, NBW, JB, 512>(p, a, st);
-    if (rb == 256 && slab_kernel_mode() == 2) return launch_slab_dma<MATH, WC, NBW, JB, 256>(p, a, st);
+    typedef typename MathTraits<MATH>::lds_t LT;
+    if constexpr (std::is_same<XT, LT>::value) {
+        if (rb == 512) return launch_slab_dma<MATH, WC, NBW, JB, 512>(p, a, st);
+        if (rb == 256) return launch_slab_dma<MATH, WC, NBW, JB, 256>(p, a, st);
+    }
     dim3 grid(unsigned(a.I1 * a.S), unsigned(p.n_j3_tiles), unsigned(p.n_j2_tiles));
     return launch("ttm_slab", st, [&] {
-        hipLaunchKernelGGL((k_slab_ws<MATH, WC, NBW, JB>), grid, dim3(WS_THREADS), 0, st, a);
+        hipLaunchKernelGGL((k_slab_ws<MATH, XT, WC, NBW, JB>), grid, dim3(WS_THREADS), 0, st, a);
     });
 }
 
@@ -1095,11 +1131,11 @@ template <int MATH, typename XT, int WC, int NBW>
 static int dispatch_slab_jb(const ChainPlan &p, const SlabArgs &a, hipStream_t st) {
     if (const int rb = dma_rowbytes<MATH, XT>(a)) {
         switch (p.JB) {
-            case 1: return launch_slab_dma_rb<MATH, WC, NBW, 1>(p, a, rb, st);
-            case 2: return launch_slab_dma_rb<MATH, WC, NBW, 2>(p, a, rb, st);
-            case 4: return launch_slab_dma_rb<MATH, WC, NBW, 4>(p, a, rb, st);
+            case 1: return launch_slab_dma_rb<MATH, XT, WC, NBW, 1>(p, a, rb, st);
+            case 2: return launch_slab_dma_rb<MATH, XT, WC, NBW, 2>(p, a, rb, st);
+            case 4: return launch_slab_dma_rb<MATH, XT, WC, NBW, 4>(p, a, rb, st);
             default:
-                if constexpr (MATH != M_F64) return launch_slab_dma_rb<MATH, WC, NBW, 8>(p, a, rb, st);
+                if constexpr (MATH != M_F64) return launch_slab_dma_rb<MATH, XT, WC, NBW, 8>(p, a, rb, st);
                 return TTM_ERR_UNSUPPORTED;
         }
     }

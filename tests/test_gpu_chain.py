@@ -251,7 +251,8 @@ def test_c3_full_size(c3_inputs, math):
 # Both slab kernels (direct-to-LDS and register-staged) on shapes where the
 # direct-to-LDS one applies: whole 256-byte chunks along i3, ragged i2 ranges.
 # ---------------------------------------------------------------------------
-DMA_SHAPES = [((7, 300, 256), (20, 35, 70)), ((3, 129, 128), (16, 130, 128)), ((2, 513, 512), (64, 64, 64))]
+DMA_SHAPES = [((7, 300, 256), (20, 35, 70)), ((3, 129, 128), (16, 130, 128)), ((2, 513, 512), (64, 64, 64)),
+              ((5, 40, 1024), (128, 128, 128))]
 
 
 @pytest.fixture
@@ -261,7 +262,7 @@ def slab_kernel_mode():
     set_slab_kernel(0)
 
 
-@pytest.mark.parametrize("mode", [0, 1], ids=["dma", "staged"])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3], ids=["copywave", "staged", "dma256", "dma512"])
 @pytest.mark.parametrize("form", [("f64", None), ("f32", None), ("bf16", torch.bfloat16), ("bf16x3", torch.bfloat16)],
                          ids=["f64", "f32", "bf16", "bf16x3"])
 @pytest.mark.parametrize("shape", DMA_SHAPES, ids=lambda s: f"I{s[0]}J{s[1]}")
@@ -280,7 +281,7 @@ def test_slab_kernels_identity_bitwise(form, slab_kernel_mode):
     I = (3, 200, 256)
     X = torch.from_numpy(rng.standard_normal(I).astype(np.float32)).to(torch.bfloat16).float().numpy()
     outs = []
-    for mode in (0, 1):
+    for mode in (0, 1, 2, 3):
         slab_kernel_mode(mode)
         Y, Xd = run(X, *[np.eye(n) for n in I], math, xdt)
         assert np.array_equal(Y, stored(Xd).astype(np.float64))
