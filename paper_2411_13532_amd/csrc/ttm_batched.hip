@@ -5,10 +5,11 @@
 // the lanes of one execution unit (Sec. 4.1, the SZ-grouped layout): here one
 // wavefront owns one cuboid at a time and its 64 lanes take the cuboid's
 // fibers.  For each of the three mode products a lane keeps one input fiber in
-// registers and produces the whole output fiber, reading the factor rows
-// from LDS (the same address on every lane, a broadcast).  X is staged into LDS
-// with coalesced loads; the intermediates of modes 3 and 2 stay in LDS; Y is
-// written with coalesced stores.  Waves take cuboids from a static
+// registers and produces the whole output fiber, reading the factor rows from
+// LDS 16 bytes at a time at the same address on every lane (a broadcast).
+// X is staged into LDS with coalesced loads; the intermediates of modes 3 and
+// 2 stay in LDS (odd strides: no bank conflicts); Y is written with coalesced
+// stores.  Waves take cuboids from a static
 // longest-first order (work ~ I1*I2*I3*J3 + ...), wave w handling positions
 // w, w + W, w + 2W, ... of that order; the launch shape (threads per block,
 // resident blocks per compute unit) is autotuned per workload and cached.
@@ -47,52 +48,73 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One fiber contraction: out[j] = sum_{e < n} U[j*n + e] * x[e] for j < m,
-// x in registers (n <= 16), U rows broadcast from LDS; fixed summation order.
+// One fiber contraction: sum_{e < n} U[e] * x[e] with x in registers
+// (x[e] = 0 for e >= n) and U a factor row in LDS, zero-padded to a multiple
+// of 4: every lane reads the same address (a broadcast), 16 bytes at a time,
+// and whole groups of 4 past n are skipped (n is wave-uniform).  Fixed order.
 template <typename T>
-__device__ __forceinline__ T dot_row(const T *__restrict__ urow, const T (&x)[BATCH_MAXN], int n) {
+__device__ __forceinline__ T dot_row(const T *urow, const T (&x)[BATCH_MAXN], int n) {
     T s = T(0);
 #pragma unroll
-    for (int e = 0; e < BATCH_MAXN; ++e)
-        if (e < n) s += urow[e] * x[e];
+    for (int e4 = 0; e4 < BATCH_MAXN / 4; ++e4) {
+        if (4 * e4 < n) {
+            T u[4];
+            __builtin_memcpy(u, urow + 4 * e4, sizeof u);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) s += u[i] * x[4 * e4 + i];
+        }
+    }
     return s;
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_batched(const BatchArgs a) {
+__global__ void __launch_bounds__(256) k_batched(const BatchArgs a, const T *__restrict__ X, const T *__restrict__ Ag,
+                                                 const T *__restrict__ Bg, const T *__restrict__ Cg,
+                                                 T *__restrict__ Y) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
     const int wpb = blockDim.x >> 6;
     const int per_wave = a.fac_elems + a.w_elems + a.xv_elems;
     T *fac = reinterpret_cast<T *>(smem_raw) + int64_t(wave) * per_wave;
     T *W = fac + a.fac_elems;
     T *XV = W + a.w_elems;
-    const T *X = static_cast<const T *>(a.X);
-    const T *Ag = static_cast<const T *>(a.A);
-    const T *Bg = static_cast<const T *>(a.B);
-    const T *Cg = static_cast<const T *>(a.C);
-    T *Y = static_cast<T *>(a.Y);
     const int64_t total_waves = int64_t(gridDim.x) * wpb;
 
     for (int64_t idx = int64_t(blockIdx.x) * wpb + wave; idx < a.count; idx += total_waves) {
         const CuboidDesc d = a.desc[idx];
         const int I1 = d.d[0], I2 = d.d[1], I3 = d.d[2], J1 = d.d[3], J2 = d.d[4], J3 = d.d[5];
-        T *As = fac, *Bs = fac + J1 * I1, *Cs = Bs + J2 * I2;
+        // factor rows padded to multiples of 4 (zeros); odd strides for fibers
+        const int P1 = (I1 + 3) & ~3, P2 = (I2 + 3) & ~3, P3 = (I3 + 3) & ~3;
+        const int SX = I3 | 1, SW = J3 | 1;
+        T *As = fac, *Bs = fac + J1 * P1, *Cs = Bs + J2 * P2;
 
-        // stage 0: factors and X into LDS, lanes on consecutive elements
-        for (int e = lane; e < J1 * I1; e += 64) As[e] = Ag[d.oa + e];
-        for (int e = lane; e < J2 * I2; e += 64) Bs[e] = Bg[d.ob + e];
-        for (int e = lane; e < J3 * I3; e += 64) Cs[e] = Cg[d.oc + e];
+        // stage 0: factors (padded) and X into LDS, lanes on consecutive elements
+        for (int e = lane; e < J1 * P1; e += 64) {
+            const int r = e / P1, c = e - r * P1;
+            As[e] = c < I1 ? Ag[d.oa + r * I1 + c] : T(0);
+        }
+        for (int e = lane; e < J2 * P2; e += 64) {
+            const int r = e / P2, c = e - r * P2;
+            Bs[e] = c < I2 ? Bg[d.ob + r * I2 + c] : T(0);
+        }
+        for (int e = lane; e < J3 * P3; e += 64) {
+            const int r = e / P3, c = e - r * P3;
+            Cs[e] = c < I3 ? Cg[d.oc + r * I3 + c] : T(0);
+        }
         const int nx = I1 * I2 * I3;
-        for (int e = lane; e < nx; e += 64) XV[e] = X[d.ox + e];
+        for (int e = lane; e < nx; e += 64) {
+            const int f = e / I3;
+            XV[f * SX + (e - f * I3)] = X[d.ox + e];
+        }
         wave_sync();
 
         // stage 1 (mode 3): fiber f = (i1, i2): W[f][j3] = sum_i3 C[j3][i3] X[f][i3]
         for (int f = lane; f < I1 * I2; f += 64) {
             T x[BATCH_MAXN];
 #pragma unroll
-            for (int e = 0; e < BATCH_MAXN; ++e) x[e] = e < I3 ? XV[f * I3 + e] : T(0);
-            for (int j = 0; j < J3; ++j) W[f * J3 + j] = dot_row(Cs + j * I3, x, I3);
+            for (int e = 0; e < BATCH_MAXN; ++e) x[e] = e < I3 ? XV[f * SX + e] : T(0);
+            for (int j = 0; j < J3; ++j) W[f * SW + j] = dot_row(Cs + j * P3, x, I3);
         }
         wave_sync();
 
@@ -102,8 +124,8 @@ __global__ void __launch_bounds__(256) k_batched(const BatchArgs a) {
             const int i1 = it / J3, j3 = it - i1 * J3;
             T w[BATCH_MAXN];
 #pragma unroll
-            for (int e = 0; e < BATCH_MAXN; ++e) w[e] = e < I2 ? W[(i1 * I2 + e) * J3 + j3] : T(0);
-            for (int j = 0; j < J2; ++j) XV[(i1 * J2 + j) * J3 + j3] = dot_row(Bs + j * I2, w, I2);
+            for (int e = 0; e < BATCH_MAXN; ++e) w[e] = e < I2 ? W[(i1 * I2 + e) * SW + j3] : T(0);
+            for (int j = 0; j < J2; ++j) XV[(i1 * J2 + j) * J3 + j3] = dot_row(Bs + j * P2, w, I2);
         }
         wave_sync();
 
@@ -113,7 +135,7 @@ __global__ void __launch_bounds__(256) k_batched(const BatchArgs a) {
             T v[BATCH_MAXN];
 #pragma unroll
             for (int e = 0; e < BATCH_MAXN; ++e) v[e] = e < I1 ? XV[e * n23 + it] : T(0);
-            for (int j = 0; j < J1; ++j) Y[d.oy + int64_t(j) * n23 + it] = dot_row(As + j * I1, v, I1);
+            for (int j = 0; j < J1; ++j) Y[d.oy + int64_t(j) * n23 + it] = dot_row(As + j * P1, v, I1);
         }
         wave_sync();
     }
@@ -140,7 +162,8 @@ struct ttm_batched_plan {
     hipGraphExec_t exec = nullptr;
     hipGraphNode_t node = nullptr;
     BatchArgs graph_args;
-    void *graph_params[1];
+    const void *graph_ptrs[5];
+    void *graph_params[6];
 };
 
 namespace {
@@ -180,9 +203,15 @@ int launch_batched(const ttm_batched_plan *p, const BatchArgs &a, int threads, i
     if (nblocks < 1) nblocks = 1;
     return launch("ttm_batched", st, [&] {
         if (p->dtype == TTM_F64)
-            hipLaunchKernelGGL(k_batched<double>, dim3(unsigned(nblocks)), dim3(threads), lds, st, a);
+            hipLaunchKernelGGL(k_batched<double>, dim3(unsigned(nblocks)), dim3(threads), lds, st, a,
+                               static_cast<const double *>(a.X), static_cast<const double *>(a.A),
+                               static_cast<const double *>(a.B), static_cast<const double *>(a.C),
+                               static_cast<double *>(a.Y));
         else
-            hipLaunchKernelGGL(k_batched<float>, dim3(unsigned(nblocks)), dim3(threads), lds, st, a);
+            hipLaunchKernelGGL(k_batched<float>, dim3(unsigned(nblocks)), dim3(threads), lds, st, a,
+                               static_cast<const float *>(a.X), static_cast<const float *>(a.A),
+                               static_cast<const float *>(a.B), static_cast<const float *>(a.C),
+                               static_cast<float *>(a.Y));
     });
 }
 
@@ -296,9 +325,10 @@ int ttm_batched_plan_create(int64_t count, const int64_t *dims_host, int dtype, 
         o[3] += d[5] * d[2];
         o[4] += d[3] * d[4] * d[5];
         work[size_t(k)] = d[0] * d[1] * d[2] * d[5] + d[0] * d[1] * d[4] * d[5] + d[0] * d[3] * d[4] * d[5];
-        p->fac_elems = std::max<int>(p->fac_elems, int(d[3] * d[0] + d[4] * d[1] + d[5] * d[2]));
-        p->w_elems = std::max<int>(p->w_elems, int(d[0] * d[1] * d[5]));
-        p->xv_elems = std::max<int>(p->xv_elems, int(std::max(d[0] * d[1] * d[2], d[0] * d[4] * d[5])));
+        p->fac_elems = std::max<int>(p->fac_elems, int(d[3] * round_up(d[0], 4) + d[4] * round_up(d[1], 4) +
+                                                       d[5] * round_up(d[2], 4)));
+        p->w_elems = std::max<int>(p->w_elems, int(d[0] * d[1] * (d[5] | 1)));
+        p->xv_elems = std::max<int>(p->xv_elems, int(std::max(d[0] * d[1] * (d[2] | 1), d[0] * d[4] * d[5])));
     }
     for (int n = 0; n < 5; ++n) p->totals[n] = o[n];
     // keep every region 16-byte aligned
@@ -399,7 +429,9 @@ int ttm_chain_batched_graph(ttm_batched_plan *p, const void *X, const void *A, c
     if (rc) return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
     p->graph_args = make_args(p, X, A, B, C, Y);
+    p->graph_ptrs[0] = X; p->graph_ptrs[1] = A; p->graph_ptrs[2] = B; p->graph_ptrs[3] = C; p->graph_ptrs[4] = Y;
     p->graph_params[0] = &p->graph_args;
+    for (int i = 0; i < 5; ++i) p->graph_params[1 + i] = &p->graph_ptrs[i];
     hipKernelNodeParams kp;
     memset(&kp, 0, sizeof kp);
     int64_t nblocks = int64_t(p->cu_count) * p->blocks_per_cu;
@@ -435,8 +467,14 @@ int ttm_chain_batched_loop(const ttm_batched_plan *p, const void *X, const void 
     for (int64_t k = 0; k < p->count; ++k) {
         a.desc = p->d_desc + k;
         const bool f64 = p->dtype == TTM_F64;
-        if (f64) hipLaunchKernelGGL(k_batched<double>, dim3(1), dim3(64), lds, st, a);
-        else hipLaunchKernelGGL(k_batched<float>, dim3(1), dim3(64), lds, st, a);
+        if (f64)
+            hipLaunchKernelGGL(k_batched<double>, dim3(1), dim3(64), lds, st, a, static_cast<const double *>(X),
+                               static_cast<const double *>(A), static_cast<const double *>(B),
+                               static_cast<const double *>(C), static_cast<double *>(Y));
+        else
+            hipLaunchKernelGGL(k_batched<float>, dim3(1), dim3(64), lds, st, a, static_cast<const float *>(X),
+                               static_cast<const float *>(A), static_cast<const float *>(B),
+                               static_cast<const float *>(C), static_cast<float *>(Y));
         if (hipGetLastError() != hipSuccess) return TTM_ERR_HIP;
     }
     return TTM_OK;
