@@ -84,12 +84,16 @@ int ttm_version(void);
  * compare the implementations of the fused mode-3/mode-2 step:
  *   0 (default): where X is already in the operand format with 16-byte
  *      aligned rows and I3 a multiple of 256 bytes, the direct-to-LDS kernel
- *      with a dedicated copy wave (three stages, two chunks in flight);
- *      the register-staged kernel elsewhere;
+ *      with 256-byte chunks and two stages; the register-staged kernel
+ *      elsewhere;
  *   1: the register-staged kernel everywhere;
- *   2: direct-to-LDS, 256-byte chunks, two stages, no copy wave;
+ *   2: direct-to-LDS, 256-byte chunks, two stages (as 0);
  *   3: direct-to-LDS, 512-byte chunks, two stages, one workgroup per
- *      compute unit (where I3 is a multiple of 512 bytes, else as 0).
+ *      compute unit (where I3 is a multiple of 512 bytes, else as 0);
+ *   4: direct-to-LDS with a dedicated copy wave (three stages, two chunks in
+ *      flight), which also widens or rounds X of another storage type while
+ *      reading it (where rows are aligned and I3 a multiple of 256 bytes,
+ *      else as 1).
  * Returns TTM_ERR_INVALID_ARG for any other value.
  */
 int ttm_set_slab_kernel(int mode);

@@ -40,7 +40,7 @@ void launch_begin(const char *name, hipStream_t s) {
     std::lock_guard<std::mutex> lk(g_mu);
     t_pending_name = name;
     t_pending_start = take_event();
-    if (t_pending_start) hipEventRecord(t_pending_start, s);
+    if (t_pending_start) (void)hipEventRecord(t_pending_start, s);
 }
 
 void launch_end(hipStream_t s) {
@@ -48,7 +48,7 @@ void launch_end(hipStream_t s) {
     std::lock_guard<std::mutex> lk(g_mu);
     hipEvent_t stop = take_event();
     if (!stop) return;
-    hipEventRecord(stop, s);
+    (void)hipEventRecord(stop, s);
     g_launches.push_back({t_pending_name ? t_pending_name : "?", t_pending_start, stop});
     t_pending_start = nullptr;
 }
@@ -89,7 +89,7 @@ const char *ttm_status_string(int status) {
 int ttm_version(void) { return 1 * 10000 + 0 * 100 + 0; }
 
 int ttm_set_slab_kernel(int mode) {
-    if (mode < 0 || mode > 3) return TTM_ERR_INVALID_ARG;
+    if (mode < 0 || mode > 4) return TTM_ERR_INVALID_ARG;
     ttm::g_slab_mode.store(mode, std::memory_order_relaxed);
     return TTM_OK;
 }

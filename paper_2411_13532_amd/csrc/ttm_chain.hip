@@ -1097,21 +1097,23 @@ static int launch_slab_dma(const ChainPlan &p, const SlabArgs &a, hipStream_t st
 }
 
 // Which direct-to-LDS variant applies (0: none): 16-byte aligned rows and
-// whole chunks along i3.  The two-stage kernels (modes 2 and 3) need X
-// already in the operand format; the copy-wave kernel widens or rounds X
-// while reading its fragments, so it takes any storage type.
+// whole chunks along i3.  The two-stage kernels (256 or 512-byte chunks) need
+// X already in the operand format; the copy-wave kernel (returned as 1) widens
+// or rounds X while reading its fragments, so it takes any storage type.
+// Automatic selection takes the two-stage 256-byte kernel where X is in the
+// operand format and the register-staged kernel otherwise: measured at
+// 1024^3 -> 128^3 the copy-wave kernel, which fits one workgroup per CU with
+// its three 32 KiB stages, runs 20-30% behind the two-stage kernel.
 template <int MATH, typename XT>
 static int dma_rowbytes(const SlabArgs &a) {
     typedef typename MathTraits<MATH>::lds_t LT;
     const int mode = slab_kernel_mode();
     if (mode == 1 || !a.x_vec || !aligned(a.X, 16)) return 0;
     const int64_t es = int64_t(sizeof(XT));
-    if (mode == 2 || mode == 3) {
-        if constexpr (!std::is_same<XT, LT>::value) return 0;
-        if (mode == 3 && a.I3 % (512 / es) == 0) return 512;
-        return a.I3 % (256 / es) == 0 ? 256 : 0;
-    }
-    return a.I3 % (256 / es) == 0 ? 1 : 0;   // copy-wave kernel
+    if (mode == 4) return a.I3 % (256 / es) == 0 ? 1 : 0;   // copy-wave kernel
+    if constexpr (!std::is_same<XT, LT>::value) return 0;
+    if (mode == 3 && a.I3 % (512 / es) == 0) return 512;
+    return a.I3 % (256 / es) == 0 ? 256 : 0;
 }
 
 template <int MATH, typename XT, int WC, int NBW, int JB>

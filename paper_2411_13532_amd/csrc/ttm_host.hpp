@@ -55,7 +55,8 @@ inline int launch(const char *name, hipStream_t s, F &&f) {
 int device_cu_count();
 
 // Slab-kernel selection set by ttm_set_slab_kernel (0 automatic, 1 register-staged,
-// 2 direct-to-LDS 256-byte chunks, 3 direct-to-LDS 512-byte chunks where possible).
+// 2 direct-to-LDS 256-byte chunks, 3 direct-to-LDS 512-byte chunks where possible,
+// 4 direct-to-LDS with a copy wave).
 int slab_kernel_mode();
 
 }  // namespace ttm

@@ -205,8 +205,9 @@ def stream_copy(dst: torch.Tensor, src: torch.Tensor) -> None:
 
 
 def set_slab_kernel(mode: int) -> None:
-    """0: automatic (default); 1: register-staged slab kernel everywhere;
-    2: direct-to-LDS with 256-byte chunks; 3: 512-byte chunks (see ttm_set_slab_kernel)."""
+    """0: automatic (default, direct-to-LDS 256-byte chunks where it applies);
+    1: register-staged everywhere; 2: direct-to-LDS 256-byte chunks; 3: 512-byte
+    chunks; 4: copy-wave direct-to-LDS kernel (see ttm_set_slab_kernel)."""
     check(_lib.load().ttm_set_slab_kernel(int(mode)), "ttm_set_slab_kernel")
 
 
