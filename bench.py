@@ -64,10 +64,17 @@ def measured_traffic(tag, per_launch_units=1.0):
     return float(t["bytes_per_launch"]) * per_launch_units
 
 
-def timed(fn, steps, warmup, torch):
+def timed(fn, steps, warmup, torch, ttm=None):
+    """Average ms per call over `steps` calls after `warmup` untimed ones.
+    With `ttm`, the library's per-launch HIP events (recorded on each kernel's
+    own stream) time every kernel over the same timed region; returns
+    (ms, wall seconds, {kernel: average ms per call of fn})."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
+    if ttm is not None:
+        ttm.timing_enable(True)
+        ttm.timing_collect()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
@@ -77,19 +84,12 @@ def timed(fn, steps, warmup, torch):
     e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return e0.elapsed_time(e1) / steps, wall
-
-
-def kernel_times(fn, steps, torch, ttm):
-    """Average duration (ms) of each library kernel over `steps` calls."""
-    ttm.timing_enable(True)
-    ttm.timing_collect()
-    for _ in range(steps):
-        fn()
-    torch.cuda.synchronize()
-    t = ttm.timing_collect()
-    ttm.timing_enable(False)
-    return {k: v[1] / v[0] for k, v in t.items()}
+    kt = None
+    if ttm is not None:
+        t = ttm.timing_collect()
+        ttm.timing_enable(False)
+        kt = {k: v[1] / steps for k, v in t.items()}
+    return e0.elapsed_time(e1) / steps, wall, kt
 
 
 def rel_err(y, ref):
@@ -116,8 +116,7 @@ def bench_dense_precision(args, torch, ttm):
                           device=dev)
         Y = torch.empty((J, J, J), dtype=torch.float32, device=dev)
         fn = lambda: ttm.chain(X, *fs, math=math, out=Y, workspace=wsm)
-        ms, wall = timed(fn, steps, args.warmup, torch)
-        kt = kernel_times(fn, min(steps, 10), torch, ttm)
+        ms, wall, kt = timed(fn, steps, args.warmup, torch, ttm)
         forms[math] = {"ms_per_step": ms, "gflops": flops / (ms * 1e-3) / 1e9, "steps": steps,
                        "kernel_ms": {k: round(v, 4) for k, v in kt.items()}}
         Ys[math] = Y.clone()
@@ -161,7 +160,7 @@ def bench_dense_precision(args, torch, ttm):
         roof = {"bound": "mfma", "achieved": round(tflops, 1), "peak": MFMA_BF16_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(tflops / MFMA_BF16_TFLOPS, 4)}
     roof["traffic"] = measured_traffic("ttm_slab_c3_bf16x3")
-    roof["kernel"] = "ttm_slab (k_slab<bf16x3, bf16 X, 4 waves x 32 columns, 8 j2 blocks>)"
+    roof["kernel"] = "ttm_slab (k_slab_dma<bf16x3, 4 waves x 32 columns, 8 j2 blocks, 256-byte chunks>)"
     roof["kernel_ms"] = round(slab_ms, 4)
     roof["algorithmic_bytes"] = slab_bytes
     roof["mfma_flops"] = slab_mfma
@@ -194,7 +193,7 @@ def copy_gbs(torch, ttm, nbytes, reps):
     """Practical HBM ceiling: read + write bytes per second of the library's copy kernel."""
     src = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
     dst = torch.empty_like(src)
-    ms, _ = timed(lambda: ttm.stream_copy(dst, src), reps, 2, torch)
+    ms, _, _ = timed(lambda: ttm.stream_copy(dst, src), reps, 2, torch)
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
@@ -221,9 +220,8 @@ def bench_c2(args, torch, ttm):
         ws = torch.empty(ttm.chain_workspace_size((I,) * 3, (J,) * 3, torch.float32, math), dtype=torch.uint8, device=dev)
         Y = torch.empty((J, J, J), dtype=torch.float32, device=dev)
         fn = lambda: ttm.chain(X, *fs, math=math, out=Y, workspace=ws)
-        ms, _ = timed(fn, args.steps, args.warmup, torch)
-        res[math] = {"ms_per_step": ms, "gflops": chain_flops(I, J) / (ms * 1e-3) / 1e9,
-                     "kernel_ms": kernel_times(fn, 10, torch, ttm)}
+        ms, _, kt = timed(fn, args.steps, args.warmup, torch, ttm)
+        res[math] = {"ms_per_step": ms, "gflops": chain_flops(I, J) / (ms * 1e-3) / 1e9, "kernel_ms": kt}
     ms = res["f32"]["ms_per_step"]
     slab = res["f32"]["kernel_ms"]["ttm_slab"]
     slab_flops = 2.0 * J * I ** 3 + 2.0 * J * J * I * I
@@ -268,7 +266,7 @@ def bench_c4(args, torch, ttm):
             torch.cuda.synchronize()
             tot += e0.elapsed_time(e1)
         res[mode] = tot / args.steps
-    ms_loop, _ = timed(lambda: plan.run(*bufs, Y=Y, mode="loop"), 2, 1, torch)
+    ms_loop, _, _ = timed(lambda: plan.run(*bufs, Y=Y, mode="loop"), 2, 1, torch)
     ms = res["graph"]
     gbs = nbytes / (ms * 1e-3) / 1e9
     return {"metric": "batched TTM-chain GFLOP/s + % roofline", "value": round(flops / (ms * 1e-3) / 1e9, 1),
@@ -290,10 +288,10 @@ def bench_c5(args, torch, ttm):
     X, A, B, C, T = (torch.from_numpy(p[k]).to(dev) for k in "XABCT")
     Y = torch.empty((J, J, J), dtype=torch.float32, device=dev)
     fwd = lambda: ttm.chain(X, A, B, C, math="f32", out=Y)
-    ms_f, _ = timed(fwd, args.steps, args.warmup, torch)
+    ms_f, _, _ = timed(fwd, args.steps, args.warmup, torch)
     G = Y - T
     bwd = lambda: ttm.chain_backward(G, X, A, B, C, math="f32")
-    ms_b, _ = timed(bwd, args.steps, args.warmup, torch)
+    ms_b, _, kt_b = timed(bwd, args.steps, args.warmup, torch, ttm)
     fl_f = chain_flops(I, J)
     return {"metric": "TTM-chain forward+adjoint GFLOP/s", "value": round(fl_f / ((ms_f) * 1e-3) / 1e9, 1),
             "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -301,7 +299,7 @@ def bench_c5(args, torch, ttm):
             "dtype": "f32", "data": "synthetic",
             "config": {"workload": "X 256^3 float32, factors 32x256 N(0,1/256), L = 1/2||Y - T||^2", "I": I, "J": J},
             "forward_ms": round(ms_f, 4), "backward_ms": round(ms_b, 4),
-            "backward_kernels_ms": kernel_times(bwd, 5, torch, ttm)}
+            "backward_kernels_ms": {k: round(v, 4) for k, v in kt_b.items()}}
 
 
 def main():
