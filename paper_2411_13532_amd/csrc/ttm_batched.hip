@@ -1,15 +1,20 @@
 // ttm_batched.hip -- many small independent chains Y_k = X_k x1 A_k x2 B_k x3 C_k
 // (ragged sizes, every mode at most 16) in one persistent launch.
 //
-// Layout on the GPU follows the paper's grouping of independent lines onto
-// the lanes of one execution unit (Sec. 4.1, the SZ-grouped layout): here one
-// wavefront owns one cuboid at a time and its 64 lanes take the cuboid's
-// fibers.  For each of the three mode products a lane keeps one input fiber in
-// registers and produces the whole output fiber, reading the factor rows from
-// LDS 16 bytes at a time at the same address on every lane (a broadcast).
-// X is staged into LDS with coalesced loads; the intermediates of modes 3 and
-// 2 stay in LDS (odd strides: no bank conflicts); Y is written with coalesced
-// stores.  Waves take cuboids from a static
+// One wavefront owns one cuboid at a time, as the paper groups independent
+// lines onto the lanes of one execution unit (Sec. 4.1, the SZ-grouped
+// layout).  In float each mode product is a row of 16 x 16 x 4 matrix-core
+// tiles (mode 3: rows (i1, i2) x columns j3; mode 2: one j2 x j3 tile per i1;
+// mode 1: rows j1 x columns (j2, j3)), operands read from LDS one element per
+// lane.  In double a lane keeps one input fiber in registers and produces the
+// whole output fiber, reading the factor rows from LDS 16 bytes at a time at
+// the same address on every lane (a broadcast).
+// The inputs of a cuboid (its three factors and X, one lane-strided
+// sequence) are loaded into registers while the wave still works on the
+// previous cuboid, so the HBM latency of one cuboid overlaps the arithmetic of
+// the one before; they then go to LDS (factor rows zero-padded, X fibers at
+// odd strides: no bank conflicts).  The intermediates of modes 3 and 2 stay in
+// LDS; Y is written with coalesced stores.  Waves take cuboids from a static
 // longest-first order (work ~ I1*I2*I3*J3 + ...), wave w handling positions
 // w, w + W, w + 2W, ... of that order; the launch shape (threads per block,
 // resident blocks per compute unit) is autotuned per workload and cached.
@@ -48,23 +53,57 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One fiber contraction: sum_{e < n} U[e] * x[e] with x in registers
-// (x[e] = 0 for e >= n) and U a factor row in LDS, zero-padded to a multiple
-// of 4: every lane reads the same address (a broadcast), 16 bytes at a time,
-// and whole groups of 4 past n are skipped (n is wave-uniform).  Fixed order.
+// Four fiber contractions at once: s[r] = sum_{e < n} U[r][e] * x[e] for
+// factor rows U[r] = urow + r * P in LDS (zero-padded to a multiple of 4) and
+// x in registers (x[e] = 0 for e >= n).  Every lane reads the same address (a
+// broadcast), 16 bytes at a time, and whole groups of 4 past n are skipped (n
+// is wave-uniform).  Four independent sums keep four LDS reads in flight.
+// Rows past the factor's last read other LDS data of the same wave; their
+// sums are discarded.  Fixed order of the terms.
 template <typename T>
-__device__ __forceinline__ T dot_row(const T *urow, const T (&x)[BATCH_MAXN], int n) {
-    T s = T(0);
+__device__ __forceinline__ void dot_rows4(const T *urow, int P, const T (&x)[BATCH_MAXN], int n, T (&s)[4]) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) s[r] = T(0);
 #pragma unroll
     for (int e4 = 0; e4 < BATCH_MAXN / 4; ++e4) {
         if (4 * e4 < n) {
-            T u[4];
-            __builtin_memcpy(u, urow + 4 * e4, sizeof u);
+            T u[4][4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) s += u[i] * x[4 * e4 + i];
+            for (int r = 0; r < 4; ++r) __builtin_memcpy(u[r], urow + r * P + 4 * e4, sizeof u[r]);
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) s[r] += u[r][i] * x[4 * e4 + i];
         }
     }
-    return s;
+}
+
+// X of the next cuboid is loaded into registers (BATCH_PF elements per lane,
+// every load issued before any is used) while the wave works on the current
+// one; a larger X loads its rest at stage 0.
+constexpr int BATCH_PF = 40;
+
+// Row r = e / len for e < 4096, len <= 16: the float quotient is at least
+// 1/32 away from the next integer, far more than its rounding error.
+__device__ __forceinline__ int row_of(int e, float inv_len) { return int((float(e) + 0.5f) * inv_len); }
+
+// n (<= 256) elements of a factor (rows of len) into LDS rows of stride P,
+// loads first (clamped, branch-free), then stores.
+template <typename T>
+__device__ __forceinline__ void factor_to_lds(const T *src, int n, int len, int P, T *dst, int lane) {
+    T r[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int e = u * 64 + lane;
+        r[u] = src[e < n ? e : n - 1];
+    }
+    const float inv = 1.0f / float(len);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int e = u * 64 + lane;
+        const int row = row_of(e, inv);
+        if (e < n) dst[row * P + (e - row * len)] = r[u];
+    }
 }
 
 template <typename T>
@@ -81,63 +120,212 @@ __global__ void __launch_bounds__(256) k_batched(const BatchArgs a, const T *__r
     T *XV = W + a.w_elems;
     const int64_t total_waves = int64_t(gridDim.x) * wpb;
 
-    for (int64_t idx = int64_t(blockIdx.x) * wpb + wave; idx < a.count; idx += total_waves) {
+    // float: the three products on the matrix cores (16x16x4 tiles, operands
+    // read from LDS with out-of-range elements replaced by zeros); double: the
+    // vector path
+    constexpr bool MF = std::is_same<T, float>::value;
+    const int r16 = lane & 15, g = lane >> 4;
+
+    T pre[BATCH_PF];
+    auto prefetch = [&](const CuboidDesc &d) {
+        const int nx = d.d[0] * d.d[1] * d.d[2];
+        const T *xs = X + d.ox;
+#pragma unroll
+        for (int u = 0; u < BATCH_PF; ++u) {
+            if (u * 64 < nx) {   // uniform: only the rows of 64 that X fills
+                const int e = u * 64 + lane;
+                pre[u] = xs[e < nx ? e : nx - 1];
+            }
+        }
+    };
+
+    int64_t idx = int64_t(blockIdx.x) * wpb + wave;
+    if (idx < a.count) prefetch(a.desc[idx]);
+    for (; idx < a.count; idx += total_waves) {
         const CuboidDesc d = a.desc[idx];
         const int I1 = d.d[0], I2 = d.d[1], I3 = d.d[2], J1 = d.d[3], J2 = d.d[4], J3 = d.d[5];
         // factor rows padded to multiples of 4 (zeros); odd strides for fibers
         const int P1 = (I1 + 3) & ~3, P2 = (I2 + 3) & ~3, P3 = (I3 + 3) & ~3;
         const int SX = I3 | 1, SW = J3 | 1;
         T *As = fac, *Bs = fac + J1 * P1, *Cs = Bs + J2 * P2;
-
-        // stage 0: factors (padded) and X into LDS, lanes on consecutive elements
-        for (int e = lane; e < J1 * P1; e += 64) {
-            const int r = e / P1, c = e - r * P1;
-            As[e] = c < I1 ? Ag[d.oa + r * I1 + c] : T(0);
-        }
-        for (int e = lane; e < J2 * P2; e += 64) {
-            const int r = e / P2, c = e - r * P2;
-            Bs[e] = c < I2 ? Bg[d.ob + r * I2 + c] : T(0);
-        }
-        for (int e = lane; e < J3 * P3; e += 64) {
-            const int r = e / P3, c = e - r * P3;
-            Cs[e] = c < I3 ? Cg[d.oc + r * I3 + c] : T(0);
-        }
         const int nx = I1 * I2 * I3;
-        for (int e = lane; e < nx; e += 64) {
-            const int f = e / I3;
-            XV[f * SX + (e - f * I3)] = X[d.ox + e];
-        }
-        wave_sync();
 
-        // stage 1 (mode 3): fiber f = (i1, i2): W[f][j3] = sum_i3 C[j3][i3] X[f][i3]
-        for (int f = lane; f < I1 * I2; f += 64) {
-            T x[BATCH_MAXN];
+        // stage 0: factors into zero-padded LDS rows, X (prefetched, plus any
+        // rest) into fibers of odd stride
+        if constexpr (!MF) {   // the vector path reads whole padded groups of 4
+            const int nfac = J1 * P1 + J2 * P2 + J3 * P3;
+            for (int e = lane; e < nfac; e += 64) fac[e] = T(0);
+            wave_sync();
+        }
+        factor_to_lds(Ag + d.oa, J1 * I1, I1, P1, As, lane);
+        factor_to_lds(Bg + d.ob, J2 * I2, I2, P2, Bs, lane);
+        factor_to_lds(Cg + d.oc, J3 * I3, I3, P3, Cs, lane);
+        const float inv3 = 1.0f / float(I3);
 #pragma unroll
-            for (int e = 0; e < BATCH_MAXN; ++e) x[e] = e < I3 ? XV[f * SX + e] : T(0);
-            for (int j = 0; j < J3; ++j) W[f * SW + j] = dot_row(Cs + j * P3, x, I3);
+        for (int u = 0; u < BATCH_PF; ++u) {
+            if (u * 64 < nx) {
+                const int e = u * 64 + lane;
+                const int f = row_of(e, inv3);
+                if (e < nx) XV[f * SX + (e - f * I3)] = pre[u];
+            }
+        }
+        for (int base = BATCH_PF * 64; base < nx; base += 16 * 64) {
+            T r[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int e = base + u * 64 + lane;
+                r[u] = X[d.ox + (e < nx ? e : nx - 1)];
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int e = base + u * 64 + lane;
+                const int f = row_of(e, inv3);
+                if (e < nx) XV[f * SX + (e - f * I3)] = r[u];
+            }
         }
         wave_sync();
+        if (idx + total_waves < a.count) prefetch(a.desc[idx + total_waves]);
 
-        // stage 2 (mode 2): fiber (i1, j3) along i2: V[i1][j2][j3] = sum_i2 B[j2][i2] W[i1][i2][j3]
-        // V overwrites X's region (X is no longer needed)
-        for (int it = lane; it < I1 * J3; it += 64) {
-            const int i1 = it / J3, j3 = it - i1 * J3;
-            T w[BATCH_MAXN];
+        if constexpr (MF) {
+            // stage 1 (mode 3): W[m][j3] = sum_i3 X[m][i3] C[j3][i3], m = (i1, i2):
+            // 16-row blocks of m, k steps of 4 along i3
+            {
+                const int M = I1 * I2, KS = (I3 + 3) >> 2;
+                float bf[4];
 #pragma unroll
-            for (int e = 0; e < BATCH_MAXN; ++e) w[e] = e < I2 ? W[(i1 * I2 + e) * SW + j3] : T(0);
-            for (int j = 0; j < J2; ++j) XV[(i1 * J2 + j) * J3 + j3] = dot_row(Bs + j * P2, w, I2);
-        }
-        wave_sync();
+                for (int ks = 0; ks < 4; ++ks) {
+                    const int k = 4 * ks + g;
+                    const bool ok = ks < KS && k < I3 && r16 < J3;
+                    bf[ks] = ok ? Cs[r16 * P3 + k] : 0.f;
+                }
+                for (int m0 = 0; m0 < M; m0 += 16) {
+                    const int m = m0 + r16;
+                    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int ks = 0; ks < 4; ++ks) {
+                        if (ks < KS) {
+                            const int k = 4 * ks + g;
+                            const bool ok = m < M && k < I3;
+                            acc = mfma_f32(ok ? XV[ok ? m * SX + k : 0] : 0.f, bf[ks], acc);
+                        }
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = m0 + 4 * g + r;
+                        if (row < M && r16 < J3) W[row * SW + r16] = acc[r];
+                    }
+                }
+            }
+            wave_sync();
+            // stage 2 (mode 2): V[i1][j2][j3] = sum_i2 B[j2][i2] W[i1][i2][j3], one
+            // 16 x 16 tile per i1; V goes to X's region at row stride NCS
+            const int NC = J2 * J3, NCS = NC | 1;
+            {
+                const int KS = (I2 + 3) >> 2;
+                float af[4];
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) {
+                    const int k = 4 * ks + g;
+                    const bool ok = ks < KS && k < I2 && r16 < J2;
+                    af[ks] = ok ? Bs[r16 * P2 + k] : 0.f;
+                }
+                for (int i1 = 0; i1 < I1; ++i1) {
+                    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int ks = 0; ks < 4; ++ks) {
+                        if (ks < KS) {
+                            const int k = 4 * ks + g;
+                            const bool ok = k < I2 && r16 < J3;
+                            acc = mfma_f32(af[ks], ok ? W[ok ? (i1 * I2 + k) * SW + r16 : 0] : 0.f, acc);
+                        }
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int j2 = 4 * g + r;
+                        if (j2 < J2 && r16 < J3) XV[i1 * NCS + j2 * J3 + r16] = acc[r];
+                    }
+                }
+            }
+            wave_sync();
+            // stage 3 (mode 1): Y[j1][c] = sum_i1 A[j1][i1] V[i1][c], c = (j2, j3):
+            // 16-column blocks of c
+            {
+                const int KS = (I1 + 3) >> 2;
+                float af[4];
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) {
+                    const int k = 4 * ks + g;
+                    const bool ok = ks < KS && k < I1 && r16 < J1;
+                    af[ks] = ok ? As[r16 * P1 + k] : 0.f;
+                }
+                for (int c0 = 0; c0 < NC; c0 += 16) {
+                    const int c = c0 + r16;
+                    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int ks = 0; ks < 4; ++ks) {
+                        if (ks < KS) {
+                            const int k = 4 * ks + g;
+                            const bool ok = k < I1 && c < NC;
+                            acc = mfma_f32(af[ks], ok ? XV[ok ? k * NCS + c : 0] : 0.f, acc);
+                        }
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int j1 = 4 * g + r;
+                        if (j1 < J1 && c < NC) Y[d.oy + int64_t(j1) * NC + c] = acc[r];
+                    }
+                }
+            }
+            wave_sync();
+        } else {
+            // stage 1 (mode 3): fiber f = (i1, i2): W[f][j3] = sum_i3 C[j3][i3] X[f][i3]
+            for (int f = lane; f < I1 * I2; f += 64) {
+                T x[BATCH_MAXN];
+#pragma unroll
+                for (int e = 0; e < BATCH_MAXN; ++e) x[e] = e < I3 ? XV[f * SX + e] : T(0);
+                for (int j = 0; j < J3; j += 4) {
+                    T o[4];
+                    dot_rows4(Cs + j * P3, P3, x, I3, o);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (j + r < J3) W[f * SW + j + r] = o[r];
+                }
+            }
+            wave_sync();
 
-        // stage 3 (mode 1): fiber (j2, j3) along i1: Y[j1][j2][j3] = sum_i1 A[j1][i1] V[i1][j2][j3]
-        const int n23 = J2 * J3;
-        for (int it = lane; it < n23; it += 64) {
-            T v[BATCH_MAXN];
+            // stage 2 (mode 2): fiber (i1, j3) along i2: V[i1][j2][j3] = sum_i2 B[j2][i2] W[i1][i2][j3]
+            // V overwrites X's region (X is no longer needed)
+            for (int it = lane; it < I1 * J3; it += 64) {
+                const int i1 = it / J3, j3 = it - i1 * J3;
+                T w[BATCH_MAXN];
 #pragma unroll
-            for (int e = 0; e < BATCH_MAXN; ++e) v[e] = e < I1 ? XV[e * n23 + it] : T(0);
-            for (int j = 0; j < J1; ++j) Y[d.oy + int64_t(j) * n23 + it] = dot_row(As + j * P1, v, I1);
+                for (int e = 0; e < BATCH_MAXN; ++e) w[e] = e < I2 ? W[(i1 * I2 + e) * SW + j3] : T(0);
+                for (int j = 0; j < J2; j += 4) {
+                    T o[4];
+                    dot_rows4(Bs + j * P2, P2, w, I2, o);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (j + r < J2) XV[(i1 * J2 + j + r) * J3 + j3] = o[r];
+                }
+            }
+            wave_sync();
+
+            // stage 3 (mode 1): fiber (j2, j3) along i1: Y[j1][j2][j3] = sum_i1 A[j1][i1] V[i1][j2][j3]
+            const int n23 = J2 * J3;
+            for (int it = lane; it < n23; it += 64) {
+                T v[BATCH_MAXN];
+#pragma unroll
+                for (int e = 0; e < BATCH_MAXN; ++e) v[e] = e < I1 ? XV[e * n23 + it] : T(0);
+                for (int j = 0; j < J1; j += 4) {
+                    T o[4];
+                    dot_rows4(As + j * P1, P1, v, I1, o);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (j + r < J1) Y[d.oy + int64_t(j + r) * n23 + it] = o[r];
+                }
+            }
+            wave_sync();
         }
-        wave_sync();
     }
 }
 
@@ -328,9 +516,11 @@ int ttm_batched_plan_create(int64_t count, const int64_t *dims_host, int dtype, 
         p->fac_elems = std::max<int>(p->fac_elems, int(d[3] * round_up(d[0], 4) + d[4] * round_up(d[1], 4) +
                                                        d[5] * round_up(d[2], 4)));
         p->w_elems = std::max<int>(p->w_elems, int(d[0] * d[1] * (d[5] | 1)));
-        p->xv_elems = std::max<int>(p->xv_elems, int(std::max(d[0] * d[1] * (d[2] | 1), d[0] * d[4] * d[5])));
+        p->xv_elems = std::max<int>(p->xv_elems, int(std::max(d[0] * d[1] * (d[2] | 1), d[0] * ((d[4] * d[5]) | 1))));
     }
     for (int n = 0; n < 5; ++n) p->totals[n] = o[n];
+    // dot_rows4 reads up to three rows (of at most 16) past a factor's last
+    p->fac_elems += 3 * BATCH_MAXN;
     // keep every region 16-byte aligned
     const int al = int(16 / p->esz);
     p->fac_elems = int(round_up(p->fac_elems, al));
