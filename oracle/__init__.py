@@ -64,6 +64,8 @@ def _load():
         lib.ttmo_backward.argtypes = [P] * 11
         lib.ttmo_backward.restype = ctypes.c_int
         lib.ttmo_batched.argtypes = [ctypes.c_int64] + [P] * 6
+        lib.ttmo_compact6_apply.argtypes = [ctypes.c_int, P] + [ctypes.c_double] * 4 + [P, P]
+        lib.ttmo_compact6_apply.restype = ctypes.c_int
         lib.ttmo_batched.restype = ctypes.c_int
         for name in ("ttmo_thomas", "ttmo_thomas_periodic"):
             getattr(lib, name).argtypes = [ctypes.c_int64] + [P] * 5
@@ -193,3 +195,17 @@ def thomas(a, b, c, d, periodic: bool = False) -> np.ndarray:
     if rc != 0:
         raise RuntimeError("thomas failed")
     return u
+
+
+def compact6_apply(X, mode: int, alpha: float, a: float, b: float, h: float) -> np.ndarray:
+    """The compact scheme of Sec. 4.2 Eq. (cfds) on a periodic grid, applied along
+    mode `mode` of X (right-hand side built per fiber, periodic Thomas solve)."""
+    Xc = _f64(X)
+    if Xc.ndim != 3:
+        raise ValueError("X must be 3-way")
+    out = np.empty_like(Xc)
+    rc = _load().ttmo_compact6_apply(int(mode), _ptr(_i64(Xc.shape)), float(alpha), float(a), float(b),
+                                     float(h), _ptr(Xc), _ptr(out))
+    if rc != 0:
+        raise ValueError("compact6_apply needs mode in 1..3 and at least 3 points along it")
+    return out

@@ -200,3 +200,46 @@ def pin_mode_order(chain_ordered_fn, seed=18):
 
 ALL_CHAIN_PINS = (pin_kronecker, pin_einsum, pin_identity, pin_rank1, pin_orthogonal_norm,
                   pin_compact6_closed_form, pin_exact_integers)
+
+
+# ---------------------------------------------------------------------------
+# Pins of the compact scheme applied along one mode without forming D
+# (apply_fn(X, mode, alpha, a, b, h) -> Y, same shape as X)
+# ---------------------------------------------------------------------------
+def pin_compact_apply_closed_form(apply_fn, shape=(16, 24, 32), ms=(3, 5, 2), rtol=1e-12):
+    """P6 on a 3-way periodic field: with X = sin(m1 x) sin(m2 y) sin(m3 z) on
+    x_i = i 2 pi / n, applying the scheme along mode k replaces sin(m_k .) by
+    k'(m_k) cos(m_k .) exactly (the Fourier mode is an eigenvector)."""
+    alpha, a, b = compact6_coefficients()
+    grids = [np.arange(n) * 2 * np.pi / n for n in shape]
+    sins = [np.sin(m * g) for m, g in zip(ms, grids)]
+    X = np.einsum("i,j,k->ijk", *sins)
+    for mode in (1, 2, 3):
+        n, m = shape[mode - 1], ms[mode - 1]
+        parts = list(sins)
+        parts[mode - 1] = compact6_modified_wavenumber(m, n) * np.cos(m * grids[mode - 1])
+        ref = np.einsum("i,j,k->ijk", *parts)
+        out = apply_fn(X, mode, alpha, a, b, 2 * np.pi / n)
+        err = rel_fro(out, ref)
+        assert err <= rtol, (mode, err)
+
+
+def pin_compact_apply_dense(apply_fn, shapes=((7, 9, 11), (5, 3, 4), (12, 6, 5)), seed=21, rtol=1e-12):
+    """The same operator as the dense mode product with D = A_c^-1 B_c (solved
+    densely), on random fields, every mode, a grid spacing not tied to n."""
+    alpha, a, b = compact6_coefficients()
+    r = np.random.default_rng(seed)
+    for shape in shapes:
+        X = r.standard_normal(shape)
+        for mode in (1, 2, 3):
+            n = shape[mode - 1]
+            h = 0.37 / n
+            Ac, Bc = compact6_periodic_matrices(n, h)
+            D = np.linalg.solve(Ac, Bc)
+            ref = np.moveaxis(np.tensordot(D, X, axes=([1], [mode - 1])), 0, mode - 1)
+            out = apply_fn(X, mode, alpha, a, b, h)
+            err = rel_fro(out, ref)
+            assert err <= rtol, (shape, mode, err)
+
+
+ALL_COMPACT_PINS = (pin_compact_apply_closed_form, pin_compact_apply_dense)

@@ -292,3 +292,78 @@ def test_c1_oracle_gaussian_statistics():
     expected = float(np.mean(np.sum(p["A"] ** 2, 1))) * float(np.mean(np.sum(p["B"] ** 2, 1))) \
         * float(np.mean(np.sum(p["C"] ** 2, 1)))
     assert abs(ms / expected - 1.0) < 0.25
+
+
+# ---------------------------------------------------------------------------
+# The compact scheme applied along a mode without forming D (Sec. 4.2)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("pin", pins.ALL_COMPACT_PINS, ids=lambda p: p.__name__)
+def test_oracle_compact_apply_pins(pin):
+    pin(oracle.compact6_apply)
+
+
+def _dense_apply(X, mode, D):
+    return np.moveaxis(np.tensordot(D, X, axes=([1], [mode - 1])), 0, mode - 1)
+
+
+def _cmut_b_sign(X, mode, alpha, a, b, h):
+    Ac, Bc = pins.compact6_periodic_matrices(X.shape[mode - 1], h)
+    _, Bm = pins.compact6_periodic_matrices(X.shape[mode - 1], h)
+    n = X.shape[mode - 1]
+    for i in range(n):   # flip the sign of the two-point-wide term only
+        Bm[i, (i + 2) % n] -= 2 * b / (4 * h)
+        Bm[i, (i - 2) % n] += 2 * b / (4 * h)
+    return _dense_apply(X, mode, np.linalg.solve(Ac, Bm))
+
+
+def _cmut_alpha_sign(X, mode, alpha, a, b, h):
+    n = X.shape[mode - 1]
+    Ac, Bc = pins.compact6_periodic_matrices(n, h)
+    Am = 2 * np.eye(n) - Ac          # alpha -> -alpha, diagonal kept
+    return _dense_apply(X, mode, np.linalg.solve(Am, Bc))
+
+
+def _cmut_no_wrap(X, mode, alpha, a, b, h):
+    n = X.shape[mode - 1]
+    Ac, Bc = pins.compact6_periodic_matrices(n, h)
+    for i in range(n):
+        for j in range(n):
+            if abs(i - j) > 2:
+                Ac[i, j] = 0.0
+                Bc[i, j] = 0.0
+    return _dense_apply(X, mode, np.linalg.solve(Ac, Bc))
+
+
+def _cmut_transposed(X, mode, alpha, a, b, h):
+    n = X.shape[mode - 1]
+    Ac, Bc = pins.compact6_periodic_matrices(n, h)
+    return _dense_apply(X, mode, np.linalg.solve(Ac, Bc).T)
+
+
+def _cmut_h_twice(X, mode, alpha, a, b, h):
+    n = X.shape[mode - 1]
+    Ac, Bc = pins.compact6_periodic_matrices(n, 2 * h)
+    return _dense_apply(X, mode, np.linalg.solve(Ac, Bc))
+
+
+def _cmut_wrong_mode(X, mode, alpha, a, b, h):
+    other = 1 + mode % 3
+    return oracle.compact6_apply(X, other, alpha, a, b, h) if X.shape[other - 1] == X.shape[mode - 1] else \
+        np.zeros_like(X)
+
+
+@pytest.mark.parametrize("mutant", [_cmut_b_sign, _cmut_alpha_sign, _cmut_no_wrap, _cmut_transposed, _cmut_h_twice,
+                                    _cmut_wrong_mode], ids=lambda m: m.__name__)
+def test_compact_planted_mistakes_are_caught(mutant):
+    failures = 0
+    for pin in pins.ALL_COMPACT_PINS:
+        try:
+            pin(mutant)
+        except AssertionError:
+            failures += 1
+    assert failures > 0, f"{mutant.__name__} passed every pin"
+
+
+def test_oracle_compact_apply_rejects_short_fibers():
+    with pytest.raises(ValueError):
+        oracle.compact6_apply(np.zeros((2, 4, 4)), 1, 1 / 3, 14 / 9, 1 / 9, 0.1)
