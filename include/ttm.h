@@ -213,6 +213,45 @@ int ttm_batched_autotune(ttm_batched_plan *plan, const void *X, const void *A,
 int ttm_batched_plan_config(const ttm_batched_plan *plan, int *out);
 
 /*
+ * The compact sixth-order first derivative of Sec. 4.2, Eq. (cfds), on a
+ * periodic grid, applied along one mode of a 3-way field:
+ *
+ *   alpha y_{i-1} + y_i + alpha y_{i+1} = a (x_{i+1} - x_{i-1}) / (2h)
+ *                                       + b (x_{i+2} - x_{i-2}) / (4h)
+ *
+ * for every fiber along `mode`, indices taken modulo n = dims[mode-1], i.e.
+ * Y = X x_mode D with D = A_c^-1 B_c (A_c the cyclic tridiagonal left side,
+ * B_c the cyclic five-point right side), evaluated without forming D: the
+ * right-hand side is built on the fly and solved as a cyclic tridiagonal
+ * system (Sec. 2.1, the periodic Thomas algorithm).  The paper's values are
+ * alpha = 1/3, a = 14/9, b = 1/9.
+ */
+typedef struct {
+    double alpha, a, b, h;   /* |alpha| < 1/2 (diagonal dominance); h != 0 */
+} ttm_compact_coef;
+
+/* Workspace bytes for fibers of n points (n >= 3) in dtype F64 or F32; 0 if
+ * unsupported. */
+size_t ttm_compact_workspace_size(int64_t n, int dtype);
+
+/*
+ * Y = the scheme applied along `mode` (1, 2 or 3) of X.
+ *   dims   host array (I1, I2, I3), each >= 1, dims[mode-1] >= 3
+ *   X, Y   device, row-major [I1][I2][I3] of dtype (F64 or F32), aligned to
+ *          the element size; Y must not overlap X or the workspace
+ *   coef   host pointer, read during the call
+ *   ws     device workspace of ttm_compact_workspace_size(dims[mode-1], dtype)
+ *          bytes (16-byte aligned), overwritten; it holds the fiber-independent
+ *          coefficients, computed on the device on `stream`
+ * Arithmetic in dtype.  Errors: TTM_ERR_INVALID_ARG (null pointer, mode out of
+ * range, sizes, non-finite or non-dominant coefficients, misalignment),
+ * TTM_ERR_UNSUPPORTED (dtype, fibers shorter than 3), TTM_ERR_WORKSPACE,
+ * TTM_ERR_ALIAS, TTM_ERR_HIP; nothing is launched on an error.
+ */
+int ttm_compact_apply(const int64_t *dims, int mode, const void *X, void *Y, int dtype,
+                      const ttm_compact_coef *coef, void *ws, size_t ws_bytes, void *stream);
+
+/*
  * Plain device-to-device copy of `bytes` (a multiple of 16; both pointers
  * 16-byte aligned, not overlapping) on `stream`: the practical HBM bandwidth
  * ceiling for the roofline, and the known-size reference for byte counters.

@@ -35,6 +35,11 @@ class Shape(ctypes.Structure):
 
 PShape = ctypes.POINTER(Shape)
 
+
+class CompactCoef(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("a", ctypes.c_double), ("b", ctypes.c_double),
+                ("h", ctypes.c_double)]
+
 SIGNATURES = {
     "ttm_status_string": (ctypes.c_char_p, [INT]),
     "ttm_version": (INT, []),
@@ -53,6 +58,8 @@ SIGNATURES = {
     "ttm_batched_autotune": (INT, [P, P, P, P, P, P, P, INT, ctypes.POINTER(ctypes.c_double)]),
     "ttm_batched_plan_config": (INT, [P, P]),
     "ttm_stream_copy": (INT, [P, P, SZ, P]),
+    "ttm_compact_workspace_size": (SZ, [I64, INT]),
+    "ttm_compact_apply": (INT, [P, INT, P, P, INT, ctypes.POINTER(CompactCoef), P, SZ, P]),
     "ttm_timing_enable": (INT, [INT]),
     "ttm_timing_collect": (INT, [P, P, P, INT]),
 }

@@ -1,0 +1,191 @@
+// ttm_compact.hip -- the compact sixth-order first derivative of Sec. 4.2,
+// Eq. (cfds), applied along one mode of a periodic 3-way field without forming
+// D = A_c^-1 B_c.  Per fiber, the five-point right-hand side is built on the
+// fly and fused with the forward pass of a cyclic tridiagonal solve (Sec. 2.1,
+// the periodic Thomas algorithm, here as a Sherman-Morrison correction of one
+// tridiagonal solve); the correction's scalar is accumulated during the
+// forward pass, so one backward pass finishes the solve.
+//
+// Splitting (gamma = -1): A_c = T + p q^T, T tridiagonal with alpha beside the
+// diagonal and diagonal 1 except T_00 = 1 - gamma, T_{n-1,n-1} = 1 - alpha^2 /
+// gamma; p = (gamma, 0, .., 0, alpha), q = (1, 0, .., 0, alpha / gamma).  With
+// T y = d and T z = p the solution is x = y - [q.y / (1 + q.z)] z.  The
+// fiber-independent data -- inv_j and cp_j of T's forward pass, z, and weights
+// w_j with y_0 = sum_j w_j y'_j (y' the forward-pass values) -- come from one
+// device thread in double precision before the sweep.
+//
+// Layout: one lane per fiber, as the paper gives each GPU thread one line of a
+// group of SZ lines (Sec. 4.1).  Row-major X makes the fibers of modes 1 and 2
+// interleaved already (lane f and f+1 read neighbouring addresses at every
+// step); mode-3 fibers are contiguous rows, read with a stride of n elements
+// per lane and served by the L1/L2 lines they share across steps.  The forward
+// pass stores y' into Y and the backward pass turns it into the solution in
+// place, so each point moves four times (read X, write y', read y', write Y);
+// the algorithmic minimum is two.
+#include <math.h>
+
+#include "ttm_device.hpp"
+#include "ttm_host.hpp"
+
+namespace ttm {
+
+namespace {
+
+struct CompactArgs {
+    int64_t n, stride, nfib, i3;   // fiber length and element stride; fibers; I3 (mode 2 mapping)
+    int64_t s12;                   // I2 * I3
+    int mode;
+    double ca, cb, alpha;          // a / (2h), b / (4h), alpha
+};
+
+// ws layout (elements of T): inv[n] | cp[n] | w[n] | z[n] | k, alpha/gamma.
+// One thread: the forward pass of T (and of T z = p) in double, then z's
+// backward pass.
+template <typename T>
+__global__ void __launch_bounds__(64) k_compact_prep(int64_t n, double alpha, T *ws) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double gamma = -1.0;
+    T *inv = ws, *cp = ws + n, *w = ws + 2 * n, *z = ws + 3 * n;
+    double cprev = 0.0, zf = 0.0, wj = 1.0;
+    for (int64_t j = 0; j < n; ++j) {
+        const double dj = (j == 0) ? 1.0 - gamma : (j == n - 1 ? 1.0 - alpha * alpha / gamma : 1.0);
+        const double iv = 1.0 / (dj - (j > 0 ? alpha * cprev : 0.0));
+        const double pj = (j == 0) ? gamma : (j == n - 1 ? alpha : 0.0);
+        zf = (pj - (j > 0 ? alpha * zf : 0.0)) * iv;
+        if (j > 0) wj = -cprev * wj;
+        cprev = alpha * iv;
+        inv[j] = T(iv);
+        cp[j] = T(cprev);
+        w[j] = T(wj);
+        z[j] = T(zf);                     // forward value, replaced below
+    }
+    const double zlast = zf;              // z_{n-1} = z'_{n-1}
+    double zn = zlast;
+    for (int64_t j = n - 2; j >= 0; --j) {
+        zn = double(z[j]) - double(cp[j]) * zn;
+        z[j] = T(zn);
+    }
+    ws[4 * n] = T(1.0 / (1.0 + zn + (alpha / gamma) * zlast));   // zn = z_0 here
+    ws[4 * n + 1] = T(alpha / gamma);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_compact(const CompactArgs a, const T *__restrict__ X, T *__restrict__ Y,
+                                                 const T *__restrict__ ws) {
+    const int64_t f = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (f >= a.nfib) return;
+    int64_t base;
+    if (a.mode == 1) base = f;
+    else if (a.mode == 2) base = (f / a.i3) * a.s12 + f % a.i3;
+    else base = f * a.n;
+    const int64_t n = a.n, s = a.stride;
+    const T *u = X + base;
+    T *y = Y + base;
+    const T *inv = ws, *cp = ws + n, *w = ws + 2 * n, *z = ws + 3 * n;
+    const T kk = ws[4 * n], ag = ws[4 * n + 1];
+    const T ca = T(a.ca), cb = T(a.cb), alpha = T(a.alpha);
+
+    // forward: d_j from the window u_{j-2} .. u_{j+2} (indices mod n), then
+    // y'_j = (d_j - alpha y'_{j-1}) inv_j, stored in Y; q.y accumulates
+    const T u0 = u[0], u1 = u[s];
+    T um2 = u[(n - 2) * s], um1 = u[(n - 1) * s], uc = u0, up1 = u1;
+    T yp = T(0), acc = T(0);
+#pragma unroll 4
+    for (int64_t j = 0; j < n; ++j) {
+        const int64_t j2 = j + 2;
+        const T up2 = j2 < n ? u[j2 * s] : (j2 == n ? u0 : u1);
+        const T d = ca * (up1 - um1) + cb * (up2 - um2);
+        yp = (d - alpha * yp) * inv[j];
+        y[j * s] = yp;
+        acc += w[j] * yp;
+        um2 = um1;
+        um1 = uc;
+        uc = up1;
+        up1 = up2;
+    }
+    // Sherman-Morrison scalar: q.y / (1 + q.z) with y_0 = acc, y_{n-1} = y'_{n-1}
+    const T sc = kk * (acc + ag * yp);
+    // backward: y_j = y'_j - cp_j y_{j+1}; x_j = y_j - sc z_j
+    T yn = yp;
+    y[(n - 1) * s] = yn - sc * z[n - 1];
+#pragma unroll 4
+    for (int64_t j = n - 2; j >= 0; --j) {
+        yn = y[j * s] - cp[j] * yn;
+        y[j * s] = yn - sc * z[j];
+    }
+}
+
+}  // namespace
+
+}  // namespace ttm
+
+using namespace ttm;
+
+extern "C" {
+
+size_t ttm_compact_workspace_size(int64_t n, int dtype) {
+    const size_t es = dtype_size(dtype);
+    if (n < 3 || (dtype != TTM_F64 && dtype != TTM_F32)) return 0;
+    return (size_t(4 * n + 2) * es + 255) & ~size_t(255);
+}
+
+int ttm_compact_apply(const int64_t *dims, int mode, const void *X, void *Y, int dtype, const ttm_compact_coef *coef,
+                      void *ws, size_t ws_bytes, void *stream) {
+    if (!dims || !X || !Y || !coef) return TTM_ERR_INVALID_ARG;
+    if (mode < 1 || mode > 3) return TTM_ERR_INVALID_ARG;
+    if (dtype != TTM_F64 && dtype != TTM_F32) return TTM_ERR_UNSUPPORTED;
+    int64_t total = 1;
+    for (int k = 0; k < 3; ++k) {
+        if (dims[k] < 1) return TTM_ERR_INVALID_ARG;
+        total = checked_prod(total, dims[k]);
+        if (total < 0) return TTM_ERR_INVALID_ARG;
+    }
+    const int64_t n = dims[mode - 1];
+    if (n < 3) return TTM_ERR_UNSUPPORTED;
+    if (!(coef->h != 0.0) || !isfinite(coef->h) || !isfinite(coef->alpha) || !isfinite(coef->a) ||
+        !isfinite(coef->b) || !(fabs(coef->alpha) < 0.5))
+        return TTM_ERR_INVALID_ARG;
+    const size_t es = dtype_size(dtype);
+    if (!aligned(X, es) || !aligned(Y, es)) return TTM_ERR_INVALID_ARG;
+    if (overlaps(X, size_t(total) * es, Y, size_t(total) * es)) return TTM_ERR_ALIAS;
+    const size_t need = ttm_compact_workspace_size(n, dtype);
+    if (!ws || ws_bytes < need || !aligned(ws, 16)) return TTM_ERR_WORKSPACE;
+    if (overlaps(ws, need, Y, size_t(total) * es) || overlaps(ws, need, X, size_t(total) * es))
+        return TTM_ERR_ALIAS;
+
+    CompactArgs a;
+    a.n = n;
+    a.mode = mode;
+    a.stride = mode == 1 ? dims[1] * dims[2] : (mode == 2 ? dims[2] : 1);
+    a.nfib = total / n;
+    a.i3 = dims[2];
+    a.s12 = dims[1] * dims[2];
+    a.ca = coef->a / (2.0 * coef->h);
+    a.cb = coef->b / (4.0 * coef->h);
+    a.alpha = coef->alpha;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const unsigned blocks = unsigned(ceil_div(a.nfib, 256));
+    int rc;
+    if (dtype == TTM_F64) {
+        rc = launch("ttm_compact_prep", st, [&] {
+            hipLaunchKernelGGL(k_compact_prep<double>, dim3(1), dim3(64), 0, st, n, coef->alpha, static_cast<double *>(ws));
+        });
+        if (rc == TTM_OK)
+            rc = launch("ttm_compact", st, [&] {
+                hipLaunchKernelGGL(k_compact<double>, dim3(blocks), dim3(256), 0, st, a, static_cast<const double *>(X),
+                                   static_cast<double *>(Y), static_cast<const double *>(ws));
+            });
+    } else {
+        rc = launch("ttm_compact_prep", st, [&] {
+            hipLaunchKernelGGL(k_compact_prep<float>, dim3(1), dim3(64), 0, st, n, coef->alpha, static_cast<float *>(ws));
+        });
+        if (rc == TTM_OK)
+            rc = launch("ttm_compact", st, [&] {
+                hipLaunchKernelGGL(k_compact<float>, dim3(blocks), dim3(256), 0, st, a, static_cast<const float *>(X),
+                                   static_cast<float *>(Y), static_cast<const float *>(ws));
+            });
+    }
+    return rc;
+}
+
+}  // extern "C"

@@ -195,6 +195,37 @@ class BatchedPlan:
         return {"threads": out[0], "blocks_per_cu": out[1], "blocks": out[2]}
 
 
+COMPACT6 = (1.0 / 3.0, 14.0 / 9.0, 1.0 / 9.0)   # alpha, a, b of Sec. 4.2 Eq. (cfds)
+
+
+def compact_apply(X: torch.Tensor, mode: int, h: float | None = None, coef=COMPACT6,
+                  out: torch.Tensor | None = None, workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """The periodic compact first-derivative scheme (alpha, a, b) = coef with grid
+    spacing h (default 2 pi / n) applied along mode 1, 2 or 3 of X (float64 or
+    float32), i.e. X x_mode A_c^-1 B_c, by fused stencil + cyclic tridiagonal solve."""
+    _need_cuda(X, out, workspace)
+    if X.dim() != 3:
+        raise ValueError("X must be 3-way")
+    if X.dtype not in (torch.float64, torch.float32):
+        raise ValueError("X must be float64 or float32")
+    n = X.shape[mode - 1] if 1 <= mode <= 3 else 0
+    if h is None:
+        h = 2.0 * 3.141592653589793 / max(n, 1)
+    if out is None:
+        out = torch.empty_like(X)
+    lib = _lib.load()
+    dt = _DT[X.dtype]
+    if workspace is None:
+        workspace = torch.empty(max(int(lib.ttm_compact_workspace_size(n, dt)), 256), dtype=torch.uint8,
+                                device=X.device)
+    dims = (ctypes.c_int64 * 3)(*X.shape)
+    c = _lib.CompactCoef(float(coef[0]), float(coef[1]), float(coef[2]), float(h))
+    rc = lib.ttm_compact_apply(dims, int(mode), _ptr(X), _ptr(out), dt, ctypes.byref(c), _ptr(workspace),
+                               workspace.numel(), _stream(X.device))
+    check(rc, "ttm_compact_apply")
+    return out
+
+
 def stream_copy(dst: torch.Tensor, src: torch.Tensor) -> None:
     """dst <- src (same byte size, 16-byte multiple) with the library's copy kernel."""
     _need_cuda(dst, src)

@@ -162,3 +162,31 @@ def test_python_binding_rejects_cpu_tensors():
     A = torch.zeros(2, 4)
     with pytest.raises(ValueError):
         chain(X, A, A, A)
+
+
+def test_compact_validation_errors(lib):
+    dims = (ctypes.c_int64 * 3)(8, 16, 32)
+    coef = _lib.CompactCoef(1 / 3, 14 / 9, 1 / 9, 0.1)
+    X, Y, ws = 0x100000, 0x900000, 0x2000000
+    need = lib.ttm_compact_workspace_size(16, _lib.TTM_F64)
+    assert need >= (4 * 16 + 2) * 8 and need % 256 == 0
+    assert lib.ttm_compact_workspace_size(2, _lib.TTM_F64) == 0
+    assert lib.ttm_compact_workspace_size(16, _lib.TTM_BF16) == 0
+    call = lambda **kw: lib.ttm_compact_apply(kw.get("dims", dims), kw.get("mode", 2), kw.get("X", X),
+                                              kw.get("Y", Y), kw.get("dt", _lib.TTM_F64),
+                                              ctypes.byref(kw.get("coef", coef)), kw.get("ws", ws),
+                                              kw.get("wsb", need), None)
+    assert call(mode=0) == _lib.TTM_ERR_INVALID_ARG
+    assert call(mode=4) == _lib.TTM_ERR_INVALID_ARG
+    assert call(dt=_lib.TTM_BF16) == _lib.TTM_ERR_UNSUPPORTED
+    assert call(dims=(ctypes.c_int64 * 3)(2, 16, 32), mode=1) == _lib.TTM_ERR_UNSUPPORTED
+    assert call(dims=(ctypes.c_int64 * 3)(0, 16, 32)) == _lib.TTM_ERR_INVALID_ARG
+    assert call(X=0) == _lib.TTM_ERR_INVALID_ARG
+    assert call(X=X + 4) == _lib.TTM_ERR_INVALID_ARG                 # misaligned for float64
+    assert call(Y=X + 8 * 100) == _lib.TTM_ERR_ALIAS                  # Y overlaps X
+    assert call(wsb=need - 8) == _lib.TTM_ERR_WORKSPACE
+    assert call(ws=0) == _lib.TTM_ERR_WORKSPACE
+    assert call(coef=_lib.CompactCoef(0.5, 14 / 9, 1 / 9, 0.1)) == _lib.TTM_ERR_INVALID_ARG   # not dominant
+    assert call(coef=_lib.CompactCoef(1 / 3, 14 / 9, 1 / 9, 0.0)) == _lib.TTM_ERR_INVALID_ARG
+    assert call(coef=_lib.CompactCoef(1 / 3, float("nan"), 1 / 9, 0.1)) == _lib.TTM_ERR_INVALID_ARG
+    assert lib.ttm_compact_apply(dims, 2, X, Y, _lib.TTM_F64, None, ws, need, None) == _lib.TTM_ERR_INVALID_ARG
