@@ -241,15 +241,20 @@ size_t ttm_compact_workspace_size(int64_t n, int dtype);
  *          the element size; Y must not overlap X or the workspace
  *   coef   host pointer, read during the call
  *   ws     device workspace of ttm_compact_workspace_size(dims[mode-1], dtype)
- *          bytes (16-byte aligned), overwritten; it holds the fiber-independent
- *          coefficients, computed on the device on `stream`
+ *          bytes (16-byte aligned); it holds the fiber-independent coefficients
+ *          of the solve (the preprocessing the paper does once per operator,
+ *          Sec. 4.2), computed on the device on `stream`
+ *   prepared  0: compute the coefficients into ws first (a short sequential
+ *          kernel, about 0.1 ms for 512 points); 1: ws already holds them
+ *          from an earlier call with the same fiber length, coef and dtype
+ *          (not checked: other contents give wrong results, never a fault)
  * Arithmetic in dtype.  Errors: TTM_ERR_INVALID_ARG (null pointer, mode out of
  * range, sizes, non-finite or non-dominant coefficients, misalignment),
  * TTM_ERR_UNSUPPORTED (dtype, fibers shorter than 3), TTM_ERR_WORKSPACE,
  * TTM_ERR_ALIAS, TTM_ERR_HIP; nothing is launched on an error.
  */
 int ttm_compact_apply(const int64_t *dims, int mode, const void *X, void *Y, int dtype,
-                      const ttm_compact_coef *coef, void *ws, size_t ws_bytes, void *stream);
+                      const ttm_compact_coef *coef, void *ws, size_t ws_bytes, int prepared, void *stream);
 
 /*
  * Plain device-to-device copy of `bytes` (a multiple of 16; both pointers

@@ -59,7 +59,7 @@ SIGNATURES = {
     "ttm_batched_plan_config": (INT, [P, P]),
     "ttm_stream_copy": (INT, [P, P, SZ, P]),
     "ttm_compact_workspace_size": (SZ, [I64, INT]),
-    "ttm_compact_apply": (INT, [P, INT, P, P, INT, ctypes.POINTER(CompactCoef), P, SZ, P]),
+    "ttm_compact_apply": (INT, [P, INT, P, P, INT, ctypes.POINTER(CompactCoef), P, SZ, INT, P]),
     "ttm_timing_enable": (INT, [INT]),
     "ttm_timing_collect": (INT, [P, P, P, INT]),
 }

@@ -45,13 +45,6 @@ struct BatchArgs {
     int fac_elems, w_elems, xv_elems;   // per-wave LDS regions (elements)
 };
 
-__device__ __forceinline__ void wave_sync() {
-    // LDS accesses of one wavefront are performed in issue order; this only
-    // stops the compiler from moving them across the stage boundary.
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // Four fiber contractions at once: s[r] = sum_{e < n} U[r][e] * x[e] for
 // factor rows U[r] = urow + r * P in LDS (zero-padded to a multiple of 4) and

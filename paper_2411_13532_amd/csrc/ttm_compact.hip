@@ -31,6 +31,8 @@ namespace ttm {
 
 namespace {
 
+constexpr int64_t COMPACT_PREP_LDS_MAX = 8192;   // fibers up to this length keep the prep in LDS
+
 struct CompactArgs {
     int64_t n, stride, nfib, i3;   // fiber length and element stride; fibers; I3 (mode 2 mapping)
     int64_t s12;                   // I2 * I3
@@ -39,13 +41,17 @@ struct CompactArgs {
 };
 
 // ws layout (elements of T): inv[n] | cp[n] | w[n] | z[n] | k, alpha/gamma.
-// One thread: the forward pass of T (and of T z = p) in double, then z's
-// backward pass.
+// One thread runs the forward pass of T (and of T z = p) in double, keeping
+// z' and cp in LDS when they fit (dynamic LDS of 16 n bytes, else read back
+// from the workspace), then z's backward pass.
 template <typename T>
 __global__ void __launch_bounds__(64) k_compact_prep(int64_t n, double alpha, T *ws) {
+    extern __shared__ __align__(16) unsigned char smem_prep[];
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const double gamma = -1.0;
     T *inv = ws, *cp = ws + n, *w = ws + 2 * n, *z = ws + 3 * n;
+    const bool lds = n <= COMPACT_PREP_LDS_MAX;
+    double *zl = reinterpret_cast<double *>(smem_prep), *cl = zl + (lds ? n : 0);
     double cprev = 0.0, zf = 0.0, wj = 1.0;
     for (int64_t j = 0; j < n; ++j) {
         const double dj = (j == 0) ? 1.0 - gamma : (j == n - 1 ? 1.0 - alpha * alpha / gamma : 1.0);
@@ -57,12 +63,14 @@ __global__ void __launch_bounds__(64) k_compact_prep(int64_t n, double alpha, T 
         inv[j] = T(iv);
         cp[j] = T(cprev);
         w[j] = T(wj);
-        z[j] = T(zf);                     // forward value, replaced below
+        if (lds) { zl[j] = zf; cl[j] = cprev; }
+        else z[j] = T(zf);                // forward value, replaced below
     }
     const double zlast = zf;              // z_{n-1} = z'_{n-1}
     double zn = zlast;
+    z[n - 1] = T(zn);
     for (int64_t j = n - 2; j >= 0; --j) {
-        zn = double(z[j]) - double(cp[j]) * zn;
+        zn = (lds ? zl[j] - cl[j] * zn : double(z[j]) - double(cp[j]) * zn);
         z[j] = T(zn);
     }
     ws[4 * n] = T(1.0 / (1.0 + zn + (alpha / gamma) * zlast));   // zn = z_0 here
@@ -72,8 +80,7 @@ __global__ void __launch_bounds__(64) k_compact_prep(int64_t n, double alpha, T 
 template <typename T>
 __global__ void __launch_bounds__(256) k_compact(const CompactArgs a, const T *__restrict__ X, T *__restrict__ Y,
                                                  const T *__restrict__ ws) {
-    const int64_t f = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    if (f >= a.nfib) return;
+    for (int64_t f = int64_t(blockIdx.x) * 256 + threadIdx.x; f < a.nfib; f += int64_t(gridDim.x) * 256) {
     int64_t base;
     if (a.mode == 1) base = f;
     else if (a.mode == 2) base = (f / a.i3) * a.s12 + f % a.i3;
@@ -113,6 +120,132 @@ __global__ void __launch_bounds__(256) k_compact(const CompactArgs a, const T *_
         yn = y[j * s] - cp[j] * yn;
         y[j * s] = yn - sc * z[j];
     }
+    }
+}
+
+// Mode 3: the fibers are contiguous rows.  A wave owns 64 rows; tiles of
+// 64 rows x RT points (128 bytes per row) go through LDS so that every global
+// access is a coalesced 16-byte-per-lane load or store, while each lane still
+// walks its own row.  Forward tiles carry a two-point halo (taken modulo n).
+// Per-wave LDS: an input tile and an output tile, rows padded by one element.
+template <typename T>
+struct RowsCfg {
+    static constexpr int VE = 16 / int(sizeof(T));    // elements per 16-byte word
+    static constexpr int RT = 128 / int(sizeof(T));   // points per tile row
+    static constexpr int WPR = RT / VE;               // 16-byte words per tile row
+    static constexpr int LD = RT + 3;                 // LDS row stride (tile + halo + pad)
+    static constexpr int WAVE_ELEMS = 2 * 64 * LD;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_compact_rows(const CompactArgs a, const T *__restrict__ X,
+                                                      T *__restrict__ Y, const T *__restrict__ ws) {
+    typedef RowsCfg<T> CF;
+    constexpr int VE = CF::VE, RT = CF::RT, LD = CF::LD;
+    extern __shared__ __align__(16) unsigned char smem_rows[];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    T *tin = reinterpret_cast<T *>(smem_rows) + wave * CF::WAVE_ELEMS;
+    T *tout = tin + 64 * LD;
+    const int64_t n = a.n;
+    const int64_t row0 = (int64_t(blockIdx.x) * (blockDim.x >> 6) + wave) * 64;
+    if (row0 >= a.nfib) return;                       // whole wave: no LDS shared across waves
+    const int64_t nrows = a.nfib - row0 < 64 ? a.nfib - row0 : 64;
+    const T *inv = ws, *cp = ws + n, *w = ws + 2 * n, *z = ws + 3 * n;
+    const T kk = ws[4 * n], ag = ws[4 * n + 1];
+    const T ca = T(a.ca), cb = T(a.cb), alpha = T(a.alpha);
+    const int64_t myrow = row0 + (lane < nrows ? lane : nrows - 1);
+    const T *urow = X + myrow * n;
+
+    // cooperative tile transfer: lane l moves word l % WPR of rows l / WPR + (64 / WPR) i
+    constexpr int WPR = CF::WPR, RPP = 64 / WPR;
+    const int wl = lane % WPR, rl = lane / WPR;
+    auto load_tile = [&](const T *src, int64_t t0, int cols) {
+#pragma unroll
+        for (int i = 0; i < WPR; ++i) {
+            const int r = rl + RPP * i;
+            const int c = wl * VE;
+            if (r < nrows && c < cols) {
+                const T *g = src + (row0 + r) * n + t0 + c;
+                if (c + VE <= cols) {
+                    V16 v = ld16(g);
+#pragma unroll
+                    for (int e = 0; e < VE; ++e) tin[r * LD + c + e] = reinterpret_cast<const T *>(&v)[e];
+                } else {
+                    for (int e = 0; c + e < cols; ++e) tin[r * LD + c + e] = g[e];
+                }
+            }
+        }
+    };
+    auto store_tile = [&](T *dst, int64_t t0, int cols) {
+#pragma unroll
+        for (int i = 0; i < WPR; ++i) {
+            const int r = rl + RPP * i;
+            const int c = wl * VE;
+            if (r < nrows && c < cols) {
+                T *g = dst + (row0 + r) * n + t0 + c;
+                if (c + VE <= cols) {
+                    V16 v;
+#pragma unroll
+                    for (int e = 0; e < VE; ++e) reinterpret_cast<T *>(&v)[e] = tout[r * LD + c + e];
+                    *reinterpret_cast<u32x4 *>(g) = v.u;
+                } else {
+                    for (int e = 0; c + e < cols; ++e) g[e] = tout[r * LD + c + e];
+                }
+            }
+        }
+    };
+
+    // forward sweep over tiles [t0, t0 + cols), halo points t0 + cols, t0 + cols + 1 (mod n)
+    T um2 = urow[n - 2], um1 = urow[n - 1], uc = urow[0], up1 = urow[1];
+    T yp = T(0), acc = T(0);
+    for (int64_t t0 = 0; t0 < n; t0 += RT) {
+        const int cols = int(n - t0 < RT ? n - t0 : RT);
+        wave_sync();
+        load_tile(X, t0, cols);
+        // the two halo points of each row (scalar loads, modulo n)
+        for (int e = lane; e < 2 * nrows; e += 64) {
+            const int r = e >> 1, h = e & 1;
+            int64_t c = t0 + cols + h;
+            if (c >= n) c -= n;
+            tin[r * LD + cols + h] = X[(row0 + r) * n + c];
+        }
+        wave_sync();
+        const T *mine = tin + lane * LD;
+        for (int c = 0; c < cols; ++c) {
+            const int64_t j = t0 + c;
+            const T up2 = mine[c + 2];
+            const T d = ca * (up1 - um1) + cb * (up2 - um2);
+            yp = (d - alpha * yp) * inv[j];
+            tout[lane * LD + c] = yp;
+            acc += w[j] * yp;
+            um2 = um1;
+            um1 = uc;
+            uc = up1;
+            up1 = up2;
+        }
+        wave_sync();
+        store_tile(Y, t0, cols);
+    }
+    const T sc = kk * (acc + ag * yp);
+
+    // backward sweep over the same tiles in reverse, in place in Y
+    T yn = T(0);
+    const int64_t last0 = ((n - 1) / RT) * RT;
+    for (int64_t t0 = last0; t0 >= 0; t0 -= RT) {
+        const int cols = int(n - t0 < RT ? n - t0 : RT);
+        wave_sync();
+        load_tile(Y, t0, cols);
+        wave_sync();
+        const T *mine = tin + lane * LD;
+        for (int c = cols - 1; c >= 0; --c) {
+            const int64_t j = t0 + c;
+            yn = mine[c] - (j == n - 1 ? T(0) : cp[j]) * yn;
+            tout[lane * LD + c] = yn - sc * z[j];
+        }
+        wave_sync();
+        store_tile(Y, t0, cols);
+    }
 }
 
 }  // namespace
@@ -130,7 +263,7 @@ size_t ttm_compact_workspace_size(int64_t n, int dtype) {
 }
 
 int ttm_compact_apply(const int64_t *dims, int mode, const void *X, void *Y, int dtype, const ttm_compact_coef *coef,
-                      void *ws, size_t ws_bytes, void *stream) {
+                      void *ws, size_t ws_bytes, int prepared, void *stream) {
     if (!dims || !X || !Y || !coef) return TTM_ERR_INVALID_ARG;
     if (mode < 1 || mode > 3) return TTM_ERR_INVALID_ARG;
     if (dtype != TTM_F64 && dtype != TTM_F32) return TTM_ERR_UNSUPPORTED;
@@ -165,21 +298,67 @@ int ttm_compact_apply(const int64_t *dims, int mode, const void *X, void *Y, int
     a.alpha = coef->alpha;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const unsigned blocks = unsigned(ceil_div(a.nfib, 256));
-    int rc;
+    // mode 3: 4 waves of 64 rows per block, each wave with its own LDS tiles
+    const unsigned row_blocks = unsigned(ceil_div(a.nfib, 256));
+    const size_t prep_lds = n <= COMPACT_PREP_LDS_MAX ? size_t(16 * n) : 0;
+    {
+        static bool prep_attr[2] = {false, false};
+        const int k = dtype == TTM_F64 ? 0 : 1;
+        if (!prep_attr[k]) {
+            const void *fn = dtype == TTM_F64 ? reinterpret_cast<const void *>(&k_compact_prep<double>)
+                                              : reinterpret_cast<const void *>(&k_compact_prep<float>);
+            if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(16 * COMPACT_PREP_LDS_MAX)) !=
+                hipSuccess)
+                return TTM_ERR_HIP;
+            prep_attr[k] = true;
+        }
+    }
+    if (mode == 3) {
+        static bool attr_set[2] = {false, false};
+        const int k = dtype == TTM_F64 ? 0 : 1;
+        if (!attr_set[k]) {
+            const void *fn = dtype == TTM_F64 ? reinterpret_cast<const void *>(&k_compact_rows<double>)
+                                              : reinterpret_cast<const void *>(&k_compact_rows<float>);
+            const int bytes = dtype == TTM_F64 ? int(4 * RowsCfg<double>::WAVE_ELEMS * sizeof(double))
+                                               : int(4 * RowsCfg<float>::WAVE_ELEMS * sizeof(float));
+            if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess)
+                return TTM_ERR_HIP;
+            attr_set[k] = true;
+        }
+    }
+    int rc = TTM_OK;
     if (dtype == TTM_F64) {
-        rc = launch("ttm_compact_prep", st, [&] {
-            hipLaunchKernelGGL(k_compact_prep<double>, dim3(1), dim3(64), 0, st, n, coef->alpha, static_cast<double *>(ws));
-        });
-        if (rc == TTM_OK)
+        if (!prepared)
+            rc = launch("ttm_compact_prep", st, [&] {
+                hipLaunchKernelGGL(k_compact_prep<double>, dim3(1), dim3(64), prep_lds, st, n, coef->alpha,
+                                   static_cast<double *>(ws));
+            });
+        if (rc == TTM_OK && mode == 3)
+            rc = launch("ttm_compact", st, [&] {
+                hipLaunchKernelGGL(k_compact_rows<double>, dim3(row_blocks), dim3(256),
+                                   4 * RowsCfg<double>::WAVE_ELEMS * sizeof(double), st, a,
+                                   static_cast<const double *>(X), static_cast<double *>(Y),
+                                   static_cast<const double *>(ws));
+            });
+        else if (rc == TTM_OK)
             rc = launch("ttm_compact", st, [&] {
                 hipLaunchKernelGGL(k_compact<double>, dim3(blocks), dim3(256), 0, st, a, static_cast<const double *>(X),
                                    static_cast<double *>(Y), static_cast<const double *>(ws));
             });
     } else {
-        rc = launch("ttm_compact_prep", st, [&] {
-            hipLaunchKernelGGL(k_compact_prep<float>, dim3(1), dim3(64), 0, st, n, coef->alpha, static_cast<float *>(ws));
-        });
-        if (rc == TTM_OK)
+        if (!prepared)
+            rc = launch("ttm_compact_prep", st, [&] {
+                hipLaunchKernelGGL(k_compact_prep<float>, dim3(1), dim3(64), prep_lds, st, n, coef->alpha,
+                                   static_cast<float *>(ws));
+            });
+        if (rc == TTM_OK && mode == 3)
+            rc = launch("ttm_compact", st, [&] {
+                hipLaunchKernelGGL(k_compact_rows<float>, dim3(row_blocks), dim3(256),
+                                   4 * RowsCfg<float>::WAVE_ELEMS * sizeof(float), st, a,
+                                   static_cast<const float *>(X), static_cast<float *>(Y),
+                                   static_cast<const float *>(ws));
+            });
+        else if (rc == TTM_OK)
             rc = launch("ttm_compact", st, [&] {
                 hipLaunchKernelGGL(k_compact<float>, dim3(blocks), dim3(256), 0, st, a, static_cast<const float *>(X),
                                    static_cast<float *>(Y), static_cast<const float *>(ws));

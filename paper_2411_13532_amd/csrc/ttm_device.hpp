@@ -157,6 +157,15 @@ __device__ __forceinline__ void dma16_to_lds(const void *g, void *lds_wave_base)
 #endif
 }
 
+// LDS accesses of one wavefront are performed in issue order; this only stops
+// the compiler from moving them across a point where the wave's lanes hand
+// data to each other through LDS.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Host/device rounding helpers for sizes.
 __host__ __device__ constexpr int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 __host__ __device__ constexpr int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }

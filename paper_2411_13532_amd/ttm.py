@@ -199,10 +199,13 @@ COMPACT6 = (1.0 / 3.0, 14.0 / 9.0, 1.0 / 9.0)   # alpha, a, b of Sec. 4.2 Eq. (c
 
 
 def compact_apply(X: torch.Tensor, mode: int, h: float | None = None, coef=COMPACT6,
-                  out: torch.Tensor | None = None, workspace: torch.Tensor | None = None) -> torch.Tensor:
+                  out: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
+                  prepared: bool = False) -> torch.Tensor:
     """The periodic compact first-derivative scheme (alpha, a, b) = coef with grid
     spacing h (default 2 pi / n) applied along mode 1, 2 or 3 of X (float64 or
-    float32), i.e. X x_mode A_c^-1 B_c, by fused stencil + cyclic tridiagonal solve."""
+    float32), i.e. X x_mode A_c^-1 B_c, by fused stencil + cyclic tridiagonal solve.
+    prepared=True reuses the coefficients an earlier call with the same fiber
+    length, coef and dtype left in `workspace`."""
     _need_cuda(X, out, workspace)
     if X.dim() != 3:
         raise ValueError("X must be 3-way")
@@ -215,13 +218,15 @@ def compact_apply(X: torch.Tensor, mode: int, h: float | None = None, coef=COMPA
         out = torch.empty_like(X)
     lib = _lib.load()
     dt = _DT[X.dtype]
+    if prepared and workspace is None:
+        raise ValueError("prepared=True needs the workspace of the earlier call")
     if workspace is None:
         workspace = torch.empty(max(int(lib.ttm_compact_workspace_size(n, dt)), 256), dtype=torch.uint8,
                                 device=X.device)
     dims = (ctypes.c_int64 * 3)(*X.shape)
     c = _lib.CompactCoef(float(coef[0]), float(coef[1]), float(coef[2]), float(h))
     rc = lib.ttm_compact_apply(dims, int(mode), _ptr(X), _ptr(out), dt, ctypes.byref(c), _ptr(workspace),
-                               workspace.numel(), _stream(X.device))
+                               workspace.numel(), 1 if prepared else 0, _stream(X.device))
     check(rc, "ttm_compact_apply")
     return out
 

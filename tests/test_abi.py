@@ -175,7 +175,7 @@ def test_compact_validation_errors(lib):
     call = lambda **kw: lib.ttm_compact_apply(kw.get("dims", dims), kw.get("mode", 2), kw.get("X", X),
                                               kw.get("Y", Y), kw.get("dt", _lib.TTM_F64),
                                               ctypes.byref(kw.get("coef", coef)), kw.get("ws", ws),
-                                              kw.get("wsb", need), None)
+                                              kw.get("wsb", need), 0, None)
     assert call(mode=0) == _lib.TTM_ERR_INVALID_ARG
     assert call(mode=4) == _lib.TTM_ERR_INVALID_ARG
     assert call(dt=_lib.TTM_BF16) == _lib.TTM_ERR_UNSUPPORTED
@@ -189,4 +189,4 @@ def test_compact_validation_errors(lib):
     assert call(coef=_lib.CompactCoef(0.5, 14 / 9, 1 / 9, 0.1)) == _lib.TTM_ERR_INVALID_ARG   # not dominant
     assert call(coef=_lib.CompactCoef(1 / 3, 14 / 9, 1 / 9, 0.0)) == _lib.TTM_ERR_INVALID_ARG
     assert call(coef=_lib.CompactCoef(1 / 3, float("nan"), 1 / 9, 0.1)) == _lib.TTM_ERR_INVALID_ARG
-    assert lib.ttm_compact_apply(dims, 2, X, Y, _lib.TTM_F64, None, ws, need, None) == _lib.TTM_ERR_INVALID_ARG
+    assert lib.ttm_compact_apply(dims, 2, X, Y, _lib.TTM_F64, None, ws, need, 0, None) == _lib.TTM_ERR_INVALID_ARG

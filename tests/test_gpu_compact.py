@@ -86,3 +86,16 @@ def test_compact_binding_errors():
         compact_apply(X, 1, out=X)                 # output aliases input
     with pytest.raises(ValueError):
         compact_apply(X.float().to(torch.bfloat16), 1)
+
+
+def test_compact_prepared_workspace_reused():
+    rng = np.random.default_rng(10)
+    X = torch.from_numpy(rng.standard_normal((30, 40, 50))).to(DEV)
+    for mode in (1, 2, 3):
+        ws = torch.empty(1 << 14, dtype=torch.uint8, device=DEV)
+        y1 = compact_apply(X, mode, workspace=ws)
+        y2 = compact_apply(X * 2, mode, workspace=ws, prepared=True)
+        assert torch.equal(y2, compact_apply(X * 2, mode))
+        assert torch.allclose(y2, 2 * y1, rtol=1e-14, atol=1e-12)
+    with pytest.raises(ValueError):
+        compact_apply(X, 1, prepared=True)
