@@ -114,8 +114,29 @@ int run_gemm(GemmArgs a, int64_t batch, bool split, void *part, hipStream_t st, 
         a.scs = a.M * a.N;
     }
     a.k_per_split = k.per;
+    // 16-byte operand loads along the unit-stride dimension where every
+    // group of VG elements stays inside the extent, the k split and one
+    // address-aligned run
+    {
+        const int64_t VG = int64_t(16 / sizeof(T));
+        const bool kk = a.K % VG == 0 && a.Ki % VG == 0 && a.k_per_split % VG == 0;
+        auto vec_ok = [&](const void *ptr, int64_t sfast_m, int64_t sk, int64_t sko, int64_t sb, int64_t sp,
+                          int64_t extent) -> int {
+            if (!aligned(ptr, 16) || sb % VG || sp % VG) return 0;
+            if (sk == 1) return (kk && sfast_m % VG == 0 && (a.Ki == a.K || sko % VG == 0)) ? 1 : 0;
+            if (sfast_m == 1) return (extent % VG == 0 && sk % VG == 0 && (a.Ki == a.K || sko % VG == 0)) ? 1 : 0;
+            return 0;
+        };
+        a.vec_a = vec_ok(a.A, a.sam, a.saki, a.sako, a.sab, 0, a.M);
+        a.vec_b = vec_ok(a.B, a.sbn, a.sbki, a.sbko, a.sbb, a.P > 1 ? a.sbp : 0, a.N);
+    }
     dim3 grid(unsigned(ceil_div(a.M, 64) * ceil_div(a.N, 64)), unsigned(k.ks), unsigned(batch));
-    int rc = launch(name, st, [&] { hipLaunchKernelGGL(k_gemm<MATH>, grid, dim3(256), 0, st, a); });
+    int rc = launch(name, st, [&] {
+        if (a.vec_a && a.vec_b) hipLaunchKernelGGL((k_gemm<MATH, true, true>), grid, dim3(256), 0, st, a);
+        else if (a.vec_a) hipLaunchKernelGGL((k_gemm<MATH, true, false>), grid, dim3(256), 0, st, a);
+        else if (a.vec_b) hipLaunchKernelGGL((k_gemm<MATH, false, true>), grid, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_gemm<MATH, false, false>), grid, dim3(256), 0, st, a);
+    });
     if (rc || k.ks == 1) return rc;
     const int64_t n = a.M * a.N;
     dim3 rg(unsigned(std::min<int64_t>(ceil_div(n, 256), 4096)));

@@ -28,6 +28,8 @@ struct GemmArgs {
     int64_t scb, scm, scn;
     int64_t k_per_split;   // k range of one grid.y split (multiple of the chunk)
     int64_t scs;           // stride between split partials in C
+    int vec_a, vec_b;      // 1: the operand's unit-stride dimension can be read 16 bytes at a time
+                           // (selects the kernel instantiation)
 };
 
 template <int MATH>
@@ -43,7 +45,8 @@ struct GemmCfg {
     static constexpr int PER = 64 * KT / 256;   // elements per thread per operand tile
 };
 
-template <int MATH>
+// VA / VB: the operand's loads are 16-byte vectors (GemmArgs::vec_a / vec_b).
+template <int MATH, bool VA, bool VB>
 __global__ void __launch_bounds__(256) k_gemm(const GemmArgs a) {
     typedef GemmCfg<MATH> CF;
     typedef typename CF::T T;
@@ -76,35 +79,85 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs a) {
     T pa[PER], pb[PER];
     auto coords = [&](bool kfast, int e, int &r, int &kk) {
         const int idx = tid + 256 * e;
-        if (kfast) { r = idx / KT; kk = idx % KT; }
-        else { kk = idx / 64; r = idx % 64; }
+        r = kfast ? idx / KT : idx % 64;
+        kk = kfast ? idx % KT : idx / 64;
+    };
+    // Vector form of the same share: group e4 of VG consecutive elements along
+    // the unit-stride dimension, read with one 16-byte load (flags set by the
+    // host where strides, extents and alignment allow it); element u of group
+    // e4 is element e4 * VG + u of the scalar share's numbering.
+    constexpr int VG = 16 / int(sizeof(T));
+    auto vcoords = [&](bool kfast, int e4, int &r, int &kk) {
+        const int idx = tid + 256 * e4;
+        r = kfast ? idx / (KT / VG) : (idx % (64 / VG)) * VG;
+        kk = kfast ? (idx % (KT / VG)) * VG : idx / (64 / VG);
+    };
+    auto kdecomp = [&](int64_t k, int64_t &ko, int64_t &ki) {
+        ko = int64_t(uint32_t(k) / uint32_t(a.Ki));
+        ki = k - ko * a.Ki;
+    };
+    auto velem = [](const V16 &v, int u) -> T {
+        if constexpr (sizeof(T) == 8) return v.d[u];
+        else return v.f[u];
     };
     // Branch-free: out-of-range elements read element (0, 0) (always valid)
     // and are zeroed, so every load of a chunk is in flight at once.
     auto fetch = [&](int64_t ch) {
         const int64_t k0 = kb + ch * KT;
+        if constexpr (VA) {
 #pragma unroll
-        for (int e = 0; e < PER; ++e) {
-            int r, kk;
-            coords(a_kfast, e, r, kk);
-            const int64_t m = m0 + r, k = k0 + kk;
-            const bool ok = m < a.M && k < ke;
-            const int64_t ko = int64_t(uint32_t(k) / uint32_t(a.Ki)), ki = k - ko * a.Ki;
-            const T v = Ap[ok ? m * a.sam + ko * a.sako + ki * a.saki : 0];
-            pa[e] = ok ? v : T(0);
+            for (int e4 = 0; e4 < PER / VG; ++e4) {
+                int r, kk;
+                vcoords(a_kfast, e4, r, kk);
+                const int64_t m = m0 + r, k = k0 + kk;
+                const bool ok = (a_kfast ? m < a.M : m + VG <= a.M) && (a_kfast ? k + VG <= ke : k < ke);
+                int64_t ko, ki;
+                kdecomp(k, ko, ki);
+                const V16 v = ld16(Ap + (ok ? m * a.sam + ko * a.sako + ki * a.saki : 0));
+#pragma unroll
+                for (int u = 0; u < VG; ++u) pa[e4 * VG + u] = ok ? velem(v, u) : T(0);
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < PER; ++e) {
+                int r, kk;
+                coords(a_kfast, e, r, kk);
+                const int64_t m = m0 + r, k = k0 + kk;
+                const bool ok = m < a.M && k < ke;
+                int64_t ko, ki;
+                kdecomp(k, ko, ki);
+                const T v = Ap[ok ? m * a.sam + ko * a.sako + ki * a.saki : 0];
+                pa[e] = ok ? v : T(0);
+            }
         }
 #pragma unroll
         for (int e = 0; e < PER; ++e) pb[e] = T(0);
         for (int p = 0; p < a.P; ++p) {
+            if constexpr (VB) {
 #pragma unroll
-            for (int e = 0; e < PER; ++e) {
-                int r, kk;
-                coords(b_kfast, e, r, kk);
-                const int64_t n = n0 + r, k = k0 + kk;
-                const bool ok = n < a.N && k < ke;
-                const int64_t ko = int64_t(uint32_t(k) / uint32_t(a.Ki)), ki = k - ko * a.Ki;
-                const T v = Bp[ok ? int64_t(p) * a.sbp + n * a.sbn + ko * a.sbko + ki * a.sbki : 0];
-                pb[e] += ok ? v : T(0);
+                for (int e4 = 0; e4 < PER / VG; ++e4) {
+                    int r, kk;
+                    vcoords(b_kfast, e4, r, kk);
+                    const int64_t n = n0 + r, k = k0 + kk;
+                    const bool ok = (b_kfast ? n < a.N : n + VG <= a.N) && (b_kfast ? k + VG <= ke : k < ke);
+                    int64_t ko, ki;
+                    kdecomp(k, ko, ki);
+                    const V16 v = ld16(Bp + (ok ? int64_t(p) * a.sbp + n * a.sbn + ko * a.sbko + ki * a.sbki : 0));
+#pragma unroll
+                    for (int u = 0; u < VG; ++u) pb[e4 * VG + u] += ok ? velem(v, u) : T(0);
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < PER; ++e) {
+                    int r, kk;
+                    coords(b_kfast, e, r, kk);
+                    const int64_t n = n0 + r, k = k0 + kk;
+                    const bool ok = n < a.N && k < ke;
+                    int64_t ko, ki;
+                    kdecomp(k, ko, ki);
+                    const T v = Bp[ok ? int64_t(p) * a.sbp + n * a.sbn + ko * a.sbko + ki * a.sbki : 0];
+                    pb[e] += ok ? v : T(0);
+                }
             }
         }
     };
@@ -119,13 +172,24 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs a) {
             *reinterpret_cast<T *>(hi + off) = v;
         }
     };
+    // element e of a share sits at (r, kk) of the scalar or of the vector numbering
+    auto ecoords = [&](bool vec, bool kfast, int e, int &r, int &kk) {
+        if (vec) {
+            vcoords(kfast, e / VG, r, kk);
+            const int du = e % VG;
+            kk += kfast ? du : 0;
+            r += kfast ? 0 : du;
+        } else {
+            coords(kfast, e, r, kk);
+        }
+    };
     auto store = [&](int buf) {
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
             int r, kk;
-            coords(a_kfast, e, r, kk);
+            ecoords(VA, a_kfast, e, r, kk);
             put(tile(0, buf, 0), CF::SPLIT ? tile(0, buf, 1) : nullptr, r, kk, pa[e]);
-            coords(b_kfast, e, r, kk);
+            ecoords(VB, b_kfast, e, r, kk);
             put(tile(1, buf, 0), CF::SPLIT ? tile(1, buf, 1) : nullptr, r, kk, pb[e]);
         }
     };
