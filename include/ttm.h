@@ -82,18 +82,25 @@ int ttm_version(void);
 /*
  * Slab-kernel selection (process-wide), for tests and measurements that
  * compare the implementations of the fused mode-3/mode-2 step:
- *   0 (default): where X is already in the operand format with 16-byte
- *      aligned rows and I3 a multiple of 256 bytes, the direct-to-LDS kernel
- *      with 256-byte chunks and two stages; the register-staged kernel
- *      elsewhere;
+ *   0 (default): with bf16 X, the bf16 or bf16x3 form and four column
+ *      waves (J3 above 32), where rows are 16-byte aligned, I3 a multiple
+ *      of 64 and the i2 range of a workgroup at least 256 rows (the grid
+ *      splits I2 into ranges of a multiple of 128 rows so as to reach about
+ *      1024 workgroups), the kernel of 5; otherwise, where X is already in the
+ *      operand format with 16-byte aligned rows and I3 a multiple of 256
+ *      bytes, the kernel of 2; the register-staged kernel elsewhere;
  *   1: the register-staged kernel everywhere;
- *   2: direct-to-LDS, 256-byte chunks, two stages (as 0);
+ *   2: direct-to-LDS, 256-byte chunks, two stages, with the fragments of C
+ *      loaded from L2 by every wave (where it applies, else as 1);
  *   3: direct-to-LDS, 512-byte chunks, two stages, one workgroup per
- *      compute unit (where I3 is a multiple of 512 bytes, else as 0);
+ *      compute unit (where I3 is a multiple of 512 bytes, else as 2);
  *   4: direct-to-LDS with a dedicated copy wave (three stages, two chunks in
  *      flight), which also widens or rounds X of another storage type while
  *      reading it (where rows are aligned and I3 a multiple of 256 bytes,
- *      else as 1).
+ *      else as 1);
+ *   5: direct-to-LDS for both X and C, eight waves over 256-row tiles,
+ *      128-byte chunks, three X stages and two C stages (where the
+ *      conditions of 0 hold, else as 1).
  * Returns TTM_ERR_INVALID_ARG for any other value.
  */
 int ttm_set_slab_kernel(int mode);

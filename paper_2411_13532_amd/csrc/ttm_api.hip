@@ -89,7 +89,7 @@ const char *ttm_status_string(int status) {
 int ttm_version(void) { return 1 * 10000 + 0 * 100 + 0; }
 
 int ttm_set_slab_kernel(int mode) {
-    if (mode < 0 || mode > 4) return TTM_ERR_INVALID_ARG;
+    if (mode < 0 || mode > 5) return TTM_ERR_INVALID_ARG;
     ttm::g_slab_mode.store(mode, std::memory_order_relaxed);
     return TTM_OK;
 }

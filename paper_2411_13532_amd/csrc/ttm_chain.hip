@@ -757,6 +757,308 @@ __global__ void __launch_bounds__(WS_THREADS, 2) k_slab_ws(const SlabArgs a) {
             }
 }
 
+// Mode-2 step for the bf16 forms with the factor loads issued in groups: W is
+// first converted to its bf16 operand pairs (freeing the accumulators), then
+// for each 32-row group the fragments of B (hi and lo) for JG j2 blocks are
+// loaded together before the matrix-core work that uses them, so a tile end
+// waits for (MB / 2) * (JB / JG) rounds of L2 latency instead of one per
+// load.  Same products and order of accumulation as slab_mode2.
+template <int MATH, int MB, int NBW, int JB, int JG>
+__device__ __forceinline__ void slab_mode2_grouped(typename MathTraits<MATH>::accv_t (&vacc)[JB][NBW],
+                                                   typename MathTraits<MATH>::accv_t (&wacc)[MB][NBW],
+                                                   const SlabArgs &a, int jbase, int64_t wrow0, int l16, int g) {
+    static_assert(MATH == M_BF16 || MATH == M_BF16X3, "bf16 forms");
+    constexpr bool X3 = MATH == M_BF16X3;
+    const uint16_t *Bh = static_cast<const uint16_t *>(a.Bhi);
+    const uint16_t *Bl = static_cast<const uint16_t *>(a.Blo);
+    u32x4 wh[MB / 2][NBW], wl[MB / 2][NBW];
+#pragma unroll
+    for (int p = 0; p < MB / 2; ++p)
+#pragma unroll
+        for (int nb = 0; nb < NBW; ++nb) {
+            const float v[8] = {wacc[2 * p][nb][0], wacc[2 * p][nb][1], wacc[2 * p][nb][2], wacc[2 * p][nb][3],
+                                wacc[2 * p + 1][nb][0], wacc[2 * p + 1][nb][1], wacc[2 * p + 1][nb][2],
+                                wacc[2 * p + 1][nb][3]};
+            if constexpr (X3) bf16_split8(v, wh[p][nb], &wl[p][nb]);
+            else wh[p][nb] = bf16_round8(v);
+        }
+#pragma unroll
+    for (int p = 0; p < MB / 2; ++p) {
+#pragma unroll
+        for (int j0 = 0; j0 < JB; j0 += JG) {
+            u32x4 bh[JG], bl[JG];
+#pragma unroll
+            for (int jj = 0; jj < JG; ++jj) {
+                const int64_t off = int64_t((jbase + j0 + jj) * 16 + l16) * a.ldb + wrow0 + 32 * p + 8 * g;
+                bh[jj] = ld16(Bh + off).u;
+                if constexpr (X3) bl[jj] = ld16(Bl + off).u;
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int jj = 0; jj < JG; ++jj)
+#pragma unroll
+                for (int nb = 0; nb < NBW; ++nb) {
+                    auto &acc = vacc[j0 + jj][nb];
+                    acc = mfma_bf16(bh[jj], wh[p][nb], acc);
+                    if constexpr (X3) {
+                        acc = mfma_bf16(bh[jj], wl[p][nb], acc);
+                        acc = mfma_bf16(bl[jj], wh[p][nb], acc);
+                    }
+                }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_slab_lc: the slab kernel with the factor C staged through LDS, for bf16 X
+// with the bf16 and bf16x3 forms where four waves share the columns (WC == 4).
+//
+// In the register-fed kernels every wave loads its own C fragments from L2
+// for every k-group of every 128-row tile: twice the bytes of X, and each of
+// those loads sits in the same in-order vector-memory queue as the X copies,
+// so its wait can include a copy.  Here one workgroup per compute unit runs
+// eight waves over 256-row tiles: the C chunk of the workgroup's columns (hi
+// and lo) is copied into LDS by the same direct-to-LDS copies as X, once per
+// workgroup and chunk, halving the C traffic, and the matrix-core waves read
+// both operands from LDS.  Wave (wr, wc) owns rows 128 wr .. 128 wr + 127 of
+// each tile and NBW column blocks.
+//
+// Chunks are 128 bytes of each row (64 values).  X has three LDS stages (two
+// chunks in flight), C two (one chunk ahead: it comes from L2).  Copies are
+// issued C(q+1) then X(q+2), so before the barrier of chunk q a wave waits
+// until at most its copies of X(q+1) are outstanding (explicit vmcnt).  The
+// stage reads are ds_read_b128 issued through inline assembly, waited for
+// with explicit lgkmcnt waits that the fragments depend on: the compiler
+// therefore never adds a wait of its own for the copies in flight, which it
+// cannot tell apart by stage.  The 16-byte words of a 128-byte row are XOR-
+// swizzled by (row >> 1) & 7: the 16 rows of a fragment read cover all 64
+// banks.  The two row halves' V partials are added through LDS at the end.
+// ---------------------------------------------------------------------------
+constexpr int LC_THREADS = 512;
+constexpr int LC_TM = 256;
+constexpr int LC_XSTAGE = LC_TM * 128;               // 32 KiB
+
+__device__ __forceinline__ uint32_t lds_offset(const void *p) {
+    return static_cast<uint32_t>(reinterpret_cast<uintptr_t>((const __attribute__((address_space(3))) char *)p));
+}
+__device__ __forceinline__ u32x4 lds_read16_async(uint32_t addr) {
+    u32x4 v;
+    asm volatile("ds_read_b128 %0, %1" : "=v"(v) : "v"(addr));
+    return v;
+}
+// wait for every LDS read in flight; the fragments become available only after it
+template <int N>
+__device__ __forceinline__ void lds_wait_all(V16 (&r)[N]) {
+    asm volatile("s_waitcnt lgkmcnt(0)");
+#pragma unroll
+    for (int i = 0; i < N; ++i) asm volatile("" : "+v"(r[i].u));
+}
+
+template <int MATH, int NBW, int JB>
+__global__ void __launch_bounds__(LC_THREADS, 1) k_slab_lc(const SlabArgs a) {
+    typedef MathTraits<MATH> TR;
+    typedef typename TR::accv_t accv_t;
+    constexpr bool X3 = MATH == M_BF16X3;
+    static_assert(MATH == M_BF16 || MATH == M_BF16X3, "bf16 forms");
+    constexpr int WC = 4, RW = 128, MB = 8;
+    constexpr int KC = 64, NKG = 2;                   // bf16 values per chunk row, k-groups per chunk
+    constexpr int COLS = WC * NBW * 16;               // columns of the workgroup
+    constexpr int CPART = COLS * 128;                 // bytes of one C part (hi or lo) per stage
+    constexpr int CSTAGE = CPART * (X3 ? 2 : 1);
+    constexpr int XOPS = LC_XSTAGE / 1024 / 8;        // X copy instructions per wave per chunk (4)
+    constexpr int COPS = CSTAGE / 1024 / 8;           // C copy instructions per wave per chunk
+    constexpr int NCF = NKG * NBW * (X3 ? 2 : 1);     // C fragments per chunk
+
+    __shared__ __align__(1024) unsigned char xbuf[3 * LC_XSTAGE];
+    __shared__ __align__(1024) unsigned char cbuf[2 * CSTAGE];
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wr = wave / WC, wc = wave % WC;
+    const int l16 = lane & 15, g = lane >> 4;
+
+    const int64_t i1 = blockIdx.x / a.S;
+    const int s = int(blockIdx.x % a.S);
+    const int64_t row_begin = int64_t(s) * a.rows_per_split;
+    const int64_t row_end = a.I2 < row_begin + a.rows_per_split ? a.I2 : row_begin + a.rows_per_split;
+    const int64_t nrows = row_end > row_begin ? row_end - row_begin : 0;
+    const int64_t colb = int64_t(blockIdx.y) * COLS;  // first column of the workgroup
+    const int jbase = int(blockIdx.z) * JB;
+    const uint16_t *Xs = static_cast<const uint16_t *>(a.X) + i1 * a.I2 * a.I3;
+    const uint16_t *Ch = static_cast<const uint16_t *>(a.Chi);
+    const uint16_t *Cl = static_cast<const uint16_t *>(a.Clo);
+    const int64_t nk = a.I3 / KC;
+    const int64_t ntiles = ceil_div(nrows, LC_TM);
+    const int64_t nq = ntiles * nk;
+
+    // copies: 8 rows (or columns) of 128 bytes per instruction; lane l fills
+    // word l % 8 of row l / 8 with logical word (l % 8) ^ ((row >> 1) & 7)
+    const int drow = lane >> 3, dpos = lane & 7;
+    auto copy_x = [&](unsigned char *stage, int64_t q) __attribute__((always_inline)) {
+        const int64_t t = q / nk, kc = q - t * nk;
+        const int64_t r0 = row_begin + t * LC_TM;
+#pragma unroll
+        for (int j = 0; j < XOPS; ++j) {
+            const int row0 = (wave * XOPS + j) * 8;
+            const int row = row0 + drow;
+            int64_t grow = r0 + row;
+            grow = grow < row_end ? grow : row_end - 1;
+            dma16_to_lds(Xs + grow * a.I3 + kc * KC + (dpos ^ ((row >> 1) & 7)) * 8, stage + row0 * 128);
+        }
+    };
+    auto copy_c = [&](unsigned char *stage, int64_t q) __attribute__((always_inline)) {
+        const int64_t kc = q % nk;
+#pragma unroll
+        for (int j = 0; j < COPS; ++j) {
+            const int idx = wave * COPS + j;           // instruction of the stage
+            const int part = idx / (COLS / 8);         // 0: hi, 1: lo
+            const int col0 = (idx % (COLS / 8)) * 8;
+            const int col = col0 + drow;
+            const uint16_t *src = (part ? Cl : Ch) + (colb + col) * a.ldc + kc * KC + (dpos ^ ((col >> 1) & 7)) * 8;
+            dma16_to_lds(src, stage + part * CPART + col0 * 128);
+        }
+    };
+
+    accv_t vacc[JB][NBW];
+    accv_t wacc[MB][NBW];
+#pragma unroll
+    for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+        for (int nb = 0; nb < NBW; ++nb) vacc[jb][nb] = zero_accv<accv_t>();
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NBW; ++nb) wacc[mb][nb] = zero_accv<accv_t>();
+
+    // per-lane LDS byte offsets of the fragment words (stage base added per chunk)
+    uint32_t xoff[NKG][MB], coff[NKG][NBW];
+#pragma unroll
+    for (int kg = 0; kg < NKG; ++kg) {
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+            const int row = wr * RW + mb * 16 + l16;
+            xoff[kg][mb] = uint32_t(row * 128 + (((kg * 4 + g) ^ ((row >> 1) & 7)) << 4));
+        }
+#pragma unroll
+        for (int nb = 0; nb < NBW; ++nb) {
+            const int col = wc * NBW * 16 + nb * 16 + l16;
+            coff[kg][nb] = uint32_t(col * 128 + (((kg * 4 + g) ^ ((col >> 1) & 7)) << 4));
+        }
+    }
+    const uint32_t xlds = lds_offset(xbuf), clds = lds_offset(cbuf);
+
+    // one chunk of matrix-core work: C fragments and the X fragments of
+    // k-group 0 first, those of k-group 1 read while k-group 0 computes
+    auto compute = [&](uint32_t xs, uint32_t cs) __attribute__((always_inline)) {
+        V16 cf[NCF], x0[MB], x1[MB];
+#pragma unroll
+        for (int kg = 0; kg < NKG; ++kg)
+#pragma unroll
+            for (int nb = 0; nb < NBW; ++nb) {
+                cf[(kg * NBW + nb) * (X3 ? 2 : 1)].u = lds_read16_async(cs + coff[kg][nb]);
+                if constexpr (X3) cf[(kg * NBW + nb) * 2 + 1].u = lds_read16_async(cs + CPART + coff[kg][nb]);
+            }
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) x0[mb].u = lds_read16_async(xs + xoff[0][mb]);
+        lds_wait_all(cf);
+        lds_wait_all(x0);
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) x1[mb].u = lds_read16_async(xs + xoff[1][mb]);
+#pragma unroll
+        for (int kg = 0; kg < NKG; ++kg) {
+            if (kg == 1) lds_wait_all(x1);
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) {
+                const u32x4 ah = kg == 0 ? x0[mb].u : x1[mb].u;
+#pragma unroll
+                for (int nb = 0; nb < NBW; ++nb) {
+                    const int c = (kg * NBW + nb) * (X3 ? 2 : 1);
+                    wacc[mb][nb] = mfma_bf16(ah, cf[c].u, wacc[mb][nb]);
+                    if constexpr (X3) wacc[mb][nb] = mfma_bf16(ah, cf[c + 1].u, wacc[mb][nb]);
+                }
+            }
+        }
+    };
+    auto tile_end = [&](int64_t t) __attribute__((always_inline)) {
+        const int64_t wrow0 = row_begin + t * LC_TM + wr * RW;
+        if (row_begin + (t + 1) * LC_TM > row_end) {
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const bool dead = wrow0 + mb * 16 + TR::acc_row(g, r) >= row_end;
+#pragma unroll
+                    for (int nb = 0; nb < NBW; ++nb)
+                        if (dead) wacc[mb][nb][r] = 0.f;
+                }
+        }
+        // rows past the range (a partial last tile) contribute zeros; B's
+        // padded columns exist up to ldb, a multiple of 128 >= every row read
+        slab_mode2_grouped<MATH, MB, NBW, JB, (JB > 4 && NBW > 1) ? JB / 2 : JB>(vacc, wacc, a, jbase, wrow0, l16, g);
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < NBW; ++nb) wacc[mb][nb] = zero_accv<accv_t>();
+    };
+
+    if (nq > 0) {
+        copy_x(xbuf, 0);
+        copy_c(cbuf, 0);
+        if (nq > 1) copy_x(xbuf + LC_XSTAGE, 1);
+    }
+    for (int64_t q = 0; q < nq; ++q) {
+        // chunk q landed everywhere: this wave's copies of X(q) and C(q) are
+        // done when at most its copies of X(q + 1) are outstanding
+        if (q + 1 < nq) wait_vmcnt<XOPS>();
+        else wait_vmcnt<0>();
+        __builtin_amdgcn_s_barrier();
+        const int xst = int(q % 3), cst = int(q & 1);
+        if (q + 1 < nq) copy_c(cbuf + (1 - cst) * CSTAGE, q + 1);
+        if (q + 2 < nq) copy_x(xbuf + ((xst + 2) % 3) * LC_XSTAGE, q + 2);
+        compute(xlds + uint32_t(xst * LC_XSTAGE), clds + uint32_t(cst * CSTAGE));
+        if (q % nk == nk - 1) tile_end(q / nk);
+    }
+
+    // the upper row half adds its V partial to the lower one's through LDS
+    // (every chunk has been consumed: the X stages are free)
+    constexpr int NV = JB * NBW * 4;
+    constexpr int PER_STAGE = LC_XSTAGE / 4 / 256;  // floats of one (wc, lane) slot per stage
+    static_assert(NV <= 2 * PER_STAGE, "reduction buffer");
+    __syncthreads();
+    auto slot = [&](int v) __attribute__((always_inline)) -> float * {   // v-th value of this (wc, lane)
+        float *base = reinterpret_cast<float *>(xbuf + (v < PER_STAGE ? 0 : LC_XSTAGE));
+        return base + ((v % PER_STAGE) * 4 + wc) * 64 + lane;
+    };
+    if (wr == 1) {
+#pragma unroll
+        for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+            for (int nb = 0; nb < NBW; ++nb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) *slot((jb * NBW + nb) * 4 + r) = vacc[jb][nb][r];
+    }
+    __syncthreads();
+    if (wr != 0) return;
+#pragma unroll
+    for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+        for (int nb = 0; nb < NBW; ++nb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) vacc[jb][nb][r] += *slot((jb * NBW + nb) * 4 + r);
+
+    float *Vp = static_cast<float *>(a.V) + (i1 * a.P + s) * a.J2pad * a.J3pad;
+#pragma unroll
+    for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+        for (int nb = 0; nb < NBW; ++nb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t j2 = int64_t(jbase + jb) * 16 + TR::acc_row(g, r);
+                Vp[j2 * a.J3pad + colb + wc * NBW * 16 + nb * 16 + l16] = vacc[jb][nb][r];
+            }
+}
+
 // ---------------------------------------------------------------------------
 // Mode-1 contraction with partial sums:
 //   Y[j1, n] = sum_i1 A[j1, i1] * sum_p V[i1][p][n],   n = j2 * J3pad + j3.
@@ -1099,18 +1401,30 @@ static int launch_slab_dma(const ChainPlan &p, const SlabArgs &a, hipStream_t st
 // Which direct-to-LDS variant applies (0: none): 16-byte aligned rows and
 // whole chunks along i3.  The two-stage kernels (256 or 512-byte chunks) need
 // X already in the operand format; the copy-wave kernel (returned as 1) widens
-// or rounds X while reading its fragments, so it takes any storage type.
-// Automatic selection takes the two-stage 256-byte kernel where X is in the
-// operand format and the register-staged kernel otherwise: measured at
-// 1024^3 -> 128^3 the copy-wave kernel, which fits one workgroup per CU with
-// its three 32 KiB stages, runs 20-30% behind the two-stage kernel.
-template <int MATH, typename XT>
+// or rounds X while reading its fragments, so it takes any storage type; the
+// kernel with C in LDS (returned as 128) takes bf16 X with the bf16 forms and
+// four column waves.  Automatic selection takes the kernel with C in LDS where
+// it applies and the row range of a workgroup holds at least one whole
+// 256-row tile (measured at 1024^3 -> 128^3 it runs 15% ahead of the
+// two-stage kernel with bf16x3 and 7% with bf16; with 128-row ranges, as at
+// 256^3 -> 64^3, half of each tile is padding), then the two-stage 256-byte kernel
+// where X is in the operand format, and the register-staged kernel otherwise:
+// the copy-wave kernel, which fits one workgroup per CU with its three 32 KiB
+// stages, runs 20-30% behind the two-stage kernel.
+template <int MATH, typename XT, int WC>
 static int dma_rowbytes(const SlabArgs &a) {
     typedef typename MathTraits<MATH>::lds_t LT;
     const int mode = slab_kernel_mode();
     if (mode == 1 || !a.x_vec || !aligned(a.X, 16)) return 0;
     const int64_t es = int64_t(sizeof(XT));
     if (mode == 4) return a.I3 % (256 / es) == 0 ? 1 : 0;   // copy-wave kernel
+    if (mode == 0 || mode == 5) {                            // C through LDS where it applies
+        if constexpr (WC == 4 && (MATH == M_BF16 || MATH == M_BF16X3) && std::is_same<XT, uint16_t>::value)
+            if (a.I3 % 64 == 0 && a.ldc % 64 == 0 && aligned(a.Chi, 16) && (!a.Clo || aligned(a.Clo, 16)) &&
+                (mode == 5 || a.rows_per_split >= LC_TM))
+                return 128;
+        if (mode == 5) return 0;
+    }
     if constexpr (!std::is_same<XT, LT>::value) return 0;
     if (mode == 3 && a.I3 % (512 / es) == 0) return 512;
     return a.I3 % (256 / es) == 0 ? 256 : 0;
@@ -1124,6 +1438,13 @@ static int launch_slab_dma_rb(const ChainPlan &p, const SlabArgs &a, int rb, hip
         if (rb == 256) return launch_slab_dma<MATH, WC, NBW, JB, 256>(p, a, st);
     }
     dim3 grid(unsigned(a.I1 * a.S), unsigned(p.n_j3_tiles), unsigned(p.n_j2_tiles));
+    if constexpr (WC == 4 && (MATH == M_BF16 || MATH == M_BF16X3) && std::is_same<XT, uint16_t>::value) {
+        if (rb == 128)
+            return launch("ttm_slab", st, [&] {
+                hipLaunchKernelGGL((k_slab_lc<MATH, NBW, JB>), grid, dim3(LC_THREADS), 0, st, a);
+            });
+    }
+    if (rb != 1) return TTM_ERR_UNSUPPORTED;
     return launch("ttm_slab", st, [&] {
         hipLaunchKernelGGL((k_slab_ws<MATH, XT, WC, NBW, JB>), grid, dim3(WS_THREADS), 0, st, a);
     });
@@ -1131,7 +1452,7 @@ static int launch_slab_dma_rb(const ChainPlan &p, const SlabArgs &a, int rb, hip
 
 template <int MATH, typename XT, int WC, int NBW>
 static int dispatch_slab_jb(const ChainPlan &p, const SlabArgs &a, hipStream_t st) {
-    if (const int rb = dma_rowbytes<MATH, XT>(a)) {
+    if (const int rb = dma_rowbytes<MATH, XT, WC>(a)) {
         switch (p.JB) {
             case 1: return launch_slab_dma_rb<MATH, XT, WC, NBW, 1>(p, a, rb, st);
             case 2: return launch_slab_dma_rb<MATH, XT, WC, NBW, 2>(p, a, rb, st);

@@ -56,7 +56,7 @@ int device_cu_count();
 
 // Slab-kernel selection set by ttm_set_slab_kernel (0 automatic, 1 register-staged,
 // 2 direct-to-LDS 256-byte chunks, 3 direct-to-LDS 512-byte chunks where possible,
-// 4 direct-to-LDS with a copy wave).
+// 4 direct-to-LDS with a copy wave, 5 X and C through LDS for bf16 X).
 int slab_kernel_mode();
 
 }  // namespace ttm

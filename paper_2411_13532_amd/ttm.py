@@ -241,9 +241,11 @@ def stream_copy(dst: torch.Tensor, src: torch.Tensor) -> None:
 
 
 def set_slab_kernel(mode: int) -> None:
-    """0: automatic (default, direct-to-LDS 256-byte chunks where it applies);
+    """0: automatic (default: X and C through LDS for bf16 X with the bf16
+    forms, else direct-to-LDS 256-byte chunks where that applies);
     1: register-staged everywhere; 2: direct-to-LDS 256-byte chunks; 3: 512-byte
-    chunks; 4: copy-wave direct-to-LDS kernel (see ttm_set_slab_kernel)."""
+    chunks; 4: copy-wave direct-to-LDS kernel; 5: X and C through LDS, eight
+    waves over 256-row tiles (see ttm_set_slab_kernel)."""
     check(_lib.load().ttm_set_slab_kernel(int(mode)), "ttm_set_slab_kernel")
 
 

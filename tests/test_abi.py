@@ -35,6 +35,13 @@ def test_every_declared_symbol_is_exported(lib):
     assert not _lib.MISSING
 
 
+def test_slab_kernel_selection_range(lib):
+    for mode in (-1, 6, 100):
+        assert lib.ttm_set_slab_kernel(mode) == -1
+    for mode in (5, 4, 3, 2, 1, 0):
+        assert lib.ttm_set_slab_kernel(mode) == 0
+
+
 def test_status_strings(lib):
     for code in (0, -1, -2, -3, -4, -5, 7):
         assert lib.ttm_status_string(code)

@@ -248,11 +248,13 @@ def test_c3_full_size(c3_inputs, math):
 
 
 # ---------------------------------------------------------------------------
-# Both slab kernels (direct-to-LDS and register-staged) on shapes where the
-# direct-to-LDS one applies: whole 256-byte chunks along i3, ragged i2 ranges.
+# Every slab kernel (direct-to-LDS variants and register-staged) on shapes
+# where the direct-to-LDS ones apply: whole 128 or 256-byte chunks along i3,
+# ragged i2 ranges, one, two and four column waves.
 # ---------------------------------------------------------------------------
 DMA_SHAPES = [((7, 300, 256), (20, 35, 70)), ((3, 129, 128), (16, 130, 128)), ((2, 513, 512), (64, 64, 64)),
-              ((5, 40, 1024), (128, 128, 128))]
+              ((5, 40, 1024), (128, 128, 128)), ((4, 517, 192), (9, 33, 100)), ((6, 70, 320), (5, 31, 24)),
+              ((2, 260, 64), (3, 12, 12))]
 
 
 @pytest.fixture
@@ -262,7 +264,7 @@ def slab_kernel_mode():
     set_slab_kernel(0)
 
 
-@pytest.mark.parametrize("mode", [0, 1, 3, 4], ids=["auto", "staged", "dma512", "copywave"])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3, 4, 5], ids=["auto", "staged", "dma256", "dma512", "copywave", "ldsc"])
 @pytest.mark.parametrize("form", [("f64", None), ("f32", None), ("bf16", torch.bfloat16), ("bf16x3", torch.bfloat16)],
                          ids=["f64", "f32", "bf16", "bf16x3"])
 @pytest.mark.parametrize("shape", DMA_SHAPES, ids=lambda s: f"I{s[0]}J{s[1]}")
@@ -281,7 +283,7 @@ def test_slab_kernels_identity_bitwise(form, slab_kernel_mode):
     I = (3, 200, 256)
     X = torch.from_numpy(rng.standard_normal(I).astype(np.float32)).to(torch.bfloat16).float().numpy()
     outs = []
-    for mode in (0, 1, 3, 4):
+    for mode in (0, 1, 2, 3, 4, 5):
         slab_kernel_mode(mode)
         Y, Xd = run(X, *[np.eye(n) for n in I], math, xdt)
         assert np.array_equal(Y, stored(Xd).astype(np.float64))
