@@ -16,6 +16,7 @@
 //      (no atomics, so every call is bitwise reproducible).
 #include <algorithm>
 #include <type_traits>
+#include <utility>
 
 #include "ttm_device.hpp"
 #include "ttm_host.hpp"
@@ -810,6 +811,62 @@ __device__ __forceinline__ void slab_mode2_grouped(typename MathTraits<MATH>::ac
     }
 }
 
+// The same step with the B loads software-pipelined: the tile's B fragments
+// are taken in rounds of four 16-row blocks of j2 (hi and lo) over 32 rows,
+// and the loads of round r + 1 are issued before the products of round r, so
+// each round waits for loads that have had a round of products to land
+// instead of a full L2 round trip.
+template <int MATH, int MB, int NBW, int JB>
+__device__ __forceinline__ void slab_mode2_pipe(typename MathTraits<MATH>::accv_t (&vacc)[JB][NBW],
+                                                typename MathTraits<MATH>::accv_t (&wacc)[MB][NBW],
+                                                const SlabArgs &a, int jbase, int64_t wrow0, int l16, int g) {
+    static_assert(MATH == M_BF16 || MATH == M_BF16X3, "bf16 forms");
+    constexpr bool X3 = MATH == M_BF16X3;
+    constexpr int JG = JB < 4 ? JB : 4, NG = JB / JG, R = (MB / 2) * NG;
+    const uint16_t *Bh = static_cast<const uint16_t *>(a.Bhi);
+    const uint16_t *Bl = static_cast<const uint16_t *>(a.Blo);
+    u32x4 wh[MB / 2][NBW], wl[MB / 2][NBW];
+#pragma unroll
+    for (int p = 0; p < MB / 2; ++p)
+#pragma unroll
+        for (int nb = 0; nb < NBW; ++nb) {
+            const float v[8] = {wacc[2 * p][nb][0], wacc[2 * p][nb][1], wacc[2 * p][nb][2], wacc[2 * p][nb][3],
+                                wacc[2 * p + 1][nb][0], wacc[2 * p + 1][nb][1], wacc[2 * p + 1][nb][2],
+                                wacc[2 * p + 1][nb][3]};
+            if constexpr (X3) bf16_split8(v, wh[p][nb], &wl[p][nb]);
+            else wh[p][nb] = bf16_round8(v);
+        }
+    u32x4 bh[2][JG], bl[2][JG];
+    auto load = [&](int r, int buf) __attribute__((always_inline)) {
+        const int p = r / NG, j0 = (r % NG) * JG;
+#pragma unroll
+        for (int jj = 0; jj < JG; ++jj) {
+            const int64_t off = int64_t((jbase + j0 + jj) * 16 + l16) * a.ldb + wrow0 + 32 * p + 8 * g;
+            bh[buf][jj] = ld16(Bh + off).u;
+            if constexpr (X3) bl[buf][jj] = ld16(Bl + off).u;
+        }
+    };
+    load(0, 0);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (r + 1 < R) load(r + 1, (r + 1) & 1);
+        __builtin_amdgcn_sched_barrier(0);
+        const int p = r / NG, j0 = (r % NG) * JG, cb = r & 1;
+#pragma unroll
+        for (int jj = 0; jj < JG; ++jj)
+#pragma unroll
+            for (int nb = 0; nb < NBW; ++nb) {
+                auto &acc = vacc[j0 + jj][nb];
+                acc = mfma_bf16(bh[cb][jj], wh[p][nb], acc);
+                if constexpr (X3) {
+                    acc = mfma_bf16(bh[cb][jj], wl[p][nb], acc);
+                    acc = mfma_bf16(bl[cb][jj], wh[p][nb], acc);
+                }
+            }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // k_slab_lc: the slab kernel with the factor C staged through LDS, for bf16 X
 // with the bf16 and bf16x3 forms where four waves share the columns (WC == 4).
@@ -842,10 +899,30 @@ constexpr int LC_XSTAGE = LC_TM * 128;               // 32 KiB
 __device__ __forceinline__ uint32_t lds_offset(const void *p) {
     return static_cast<uint32_t>(reinterpret_cast<uintptr_t>((const __attribute__((address_space(3))) char *)p));
 }
-__device__ __forceinline__ u32x4 lds_read16_async(uint32_t addr) {
+// Direct-to-LDS copy of 16 bytes per lane to LDS byte address m0 + 16 lane,
+// issued through inline assembly so that the compiler does not count it among
+// the vector-memory operations it waits for: its own waits for ordinary loads
+// (which return in order among themselves) then count only those loads
+// instead of falling back to waiting for everything, and the copies are waited
+// for explicitly.  No other code of the kernel that uses this relies on m0.
+__device__ __forceinline__ void dma16_to_lds_m0(const void *g, uint32_t lds_addr) {
+    asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" : : "v"(g), "s"(lds_addr));
+}
+template <int OFF>
+__device__ __forceinline__ u32x4 lds_read16_at(uint32_t addr) {
+    static_assert(OFF >= 0 && OFF < 65536 && OFF % 16 == 0, "ds_read_b128 immediate offset");
     u32x4 v;
-    asm volatile("ds_read_b128 %0, %1" : "=v"(v) : "v"(addr));
+    asm volatile("ds_read_b128 %0, %1 offset:%2" : "=v"(v) : "v"(addr), "i"(OFF));
     return v;
+}
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_seq(F &&f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+// f(std::integral_constant<int, i>) for i = 0 .. N - 1, in order
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    static_for_seq(f, std::make_integer_sequence<int, N>{});
 }
 // wait for every LDS read in flight; the fragments become available only after it
 template <int N>
@@ -893,30 +970,48 @@ __global__ void __launch_bounds__(LC_THREADS, 1) k_slab_lc(const SlabArgs a) {
     const int64_t nq = ntiles * nk;
 
     // copies: 8 rows (or columns) of 128 bytes per instruction; lane l fills
-    // word l % 8 of row l / 8 with logical word (l % 8) ^ ((row >> 1) & 7)
+    // word l % 8 of row l / 8 with logical word (l % 8) ^ ((row >> 1) & 7).
+    // Addresses are a uniform base plus a 32-bit lane offset (the host
+    // guarantees 256 rows of X and the columns of C span less than 4 GiB);
+    // X's lane offsets change only at a tile whose rows run past the range,
+    // where rows are clamped to the last one.
     const int drow = lane >> 3, dpos = lane & 7;
-    auto copy_x = [&](unsigned char *stage, int64_t q) __attribute__((always_inline)) {
-        const int64_t t = q / nk, kc = q - t * nk;
-        const int64_t r0 = row_begin + t * LC_TM;
+    const int64_t xrow_bytes = a.I3 * 2, crow_bytes = a.ldc * 2;
+    uint32_t xlo[XOPS], clo[COPS];
+    const uint32_t xrow_b32 = uint32_t(xrow_bytes);
+    auto set_x_offsets = [&](int64_t r0) __attribute__((always_inline)) {
+        // last row of the range relative to the tile, at most LC_TM - 1
+        const int64_t last64 = row_end - 1 - r0;
+        const int last = __builtin_amdgcn_readfirstlane(int(last64 < LC_TM - 1 ? last64 : LC_TM - 1));
 #pragma unroll
         for (int j = 0; j < XOPS; ++j) {
-            const int row0 = (wave * XOPS + j) * 8;
-            const int row = row0 + drow;
-            int64_t grow = r0 + row;
-            grow = grow < row_end ? grow : row_end - 1;
-            dma16_to_lds(Xs + grow * a.I3 + kc * KC + (dpos ^ ((row >> 1) & 7)) * 8, stage + row0 * 128);
+            const int row = (wave * XOPS + j) * 8 + drow;
+            const uint32_t rr = uint32_t(row < last ? row : last);
+            xlo[j] = rr * xrow_b32 + uint32_t((dpos ^ ((row >> 1) & 7)) << 4);
         }
     };
-    auto copy_c = [&](unsigned char *stage, int64_t q) __attribute__((always_inline)) {
-        const int64_t kc = q % nk;
+#pragma unroll
+    for (int j = 0; j < COPS; ++j) {
+        const int idx = wave * COPS + j;
+        const int col = (idx % (COLS / 8)) * 8 + drow;
+        clo[j] = uint32_t(col) * uint32_t(crow_bytes) + uint32_t((dpos ^ ((col >> 1) & 7)) << 4);
+    }
+    const char *xslab = reinterpret_cast<const char *>(Xs);
+    const char *cbase[2] = {reinterpret_cast<const char *>(Ch + colb * a.ldc),
+                            reinterpret_cast<const char *>((X3 ? Cl : Ch) + colb * a.ldc)};
+    // stage arguments are LDS byte addresses
+    auto copy_x = [&](uint32_t stage, int64_t t, int kc) __attribute__((always_inline)) {
+        const char *base = xslab + (row_begin + t * LC_TM) * xrow_bytes + kc * 128;
+#pragma unroll
+        for (int j = 0; j < XOPS; ++j) dma16_to_lds_m0(base + xlo[j], stage + uint32_t((wave * XOPS + j) * 8 * 128));
+    };
+    auto copy_c = [&](uint32_t stage, int kc) __attribute__((always_inline)) {
 #pragma unroll
         for (int j = 0; j < COPS; ++j) {
-            const int idx = wave * COPS + j;           // instruction of the stage
+            const int idx = wave * COPS + j;
             const int part = idx / (COLS / 8);         // 0: hi, 1: lo
             const int col0 = (idx % (COLS / 8)) * 8;
-            const int col = col0 + drow;
-            const uint16_t *src = (part ? Cl : Ch) + (colb + col) * a.ldc + kc * KC + (dpos ^ ((col >> 1) & 7)) * 8;
-            dma16_to_lds(src, stage + part * CPART + col0 * 128);
+            dma16_to_lds_m0(cbase[part] + kc * 128 + clo[j], stage + uint32_t(part * CPART + col0 * 128));
         }
     };
 
@@ -931,20 +1026,15 @@ __global__ void __launch_bounds__(LC_THREADS, 1) k_slab_lc(const SlabArgs a) {
 #pragma unroll
         for (int nb = 0; nb < NBW; ++nb) wacc[mb][nb] = zero_accv<accv_t>();
 
-    // per-lane LDS byte offsets of the fragment words (stage base added per chunk)
-    uint32_t xoff[NKG][MB], coff[NKG][NBW];
+    // per-lane LDS byte offsets of the fragment words of k-group kg: the
+    // swizzle key (row >> 1) & 7 of rows 16 m + l16 is (l16 >> 1) & 7 for
+    // every 16-row block, so block m adds the immediate m * 2048
+    uint32_t xl[NKG], cl[NKG];
 #pragma unroll
     for (int kg = 0; kg < NKG; ++kg) {
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-            const int row = wr * RW + mb * 16 + l16;
-            xoff[kg][mb] = uint32_t(row * 128 + (((kg * 4 + g) ^ ((row >> 1) & 7)) << 4));
-        }
-#pragma unroll
-        for (int nb = 0; nb < NBW; ++nb) {
-            const int col = wc * NBW * 16 + nb * 16 + l16;
-            coff[kg][nb] = uint32_t(col * 128 + (((kg * 4 + g) ^ ((col >> 1) & 7)) << 4));
-        }
+        const uint32_t w = uint32_t(((kg * 4 + g) ^ ((l16 >> 1) & 7)) << 4);
+        xl[kg] = uint32_t((wr * RW + l16) * 128) + w;
+        cl[kg] = uint32_t((wc * NBW * 16 + l16) * 128) + w;
     }
     const uint32_t xlds = lds_offset(xbuf), clds = lds_offset(cbuf);
 
@@ -952,19 +1042,17 @@ __global__ void __launch_bounds__(LC_THREADS, 1) k_slab_lc(const SlabArgs a) {
     // k-group 0 first, those of k-group 1 read while k-group 0 computes
     auto compute = [&](uint32_t xs, uint32_t cs) __attribute__((always_inline)) {
         V16 cf[NCF], x0[MB], x1[MB];
-#pragma unroll
-        for (int kg = 0; kg < NKG; ++kg)
-#pragma unroll
-            for (int nb = 0; nb < NBW; ++nb) {
-                cf[(kg * NBW + nb) * (X3 ? 2 : 1)].u = lds_read16_async(cs + coff[kg][nb]);
-                if constexpr (X3) cf[(kg * NBW + nb) * 2 + 1].u = lds_read16_async(cs + CPART + coff[kg][nb]);
-            }
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb) x0[mb].u = lds_read16_async(xs + xoff[0][mb]);
+        const uint32_t xa0 = xs + xl[0], xa1 = xs + xl[1];
+        const uint32_t ca[NKG] = {cs + cl[0], cs + cl[1]};
+        static_for<NKG * NBW>([&](auto i) __attribute__((always_inline)) {
+            constexpr int kg = decltype(i)::value / NBW, nb = decltype(i)::value % NBW;
+            cf[i * (X3 ? 2 : 1)].u = lds_read16_at<nb * 2048>(ca[kg]);
+            if constexpr (X3) cf[i * 2 + 1].u = lds_read16_at<CPART + nb * 2048>(ca[kg]);
+        });
+        static_for<MB>([&](auto m) __attribute__((always_inline)) { x0[m].u = lds_read16_at<decltype(m)::value * 2048>(xa0); });
         lds_wait_all(cf);
         lds_wait_all(x0);
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb) x1[mb].u = lds_read16_async(xs + xoff[1][mb]);
+        static_for<MB>([&](auto m) __attribute__((always_inline)) { x1[m].u = lds_read16_at<decltype(m)::value * 2048>(xa1); });
 #pragma unroll
         for (int kg = 0; kg < NKG; ++kg) {
             if (kg == 1) lds_wait_all(x1);
@@ -982,42 +1070,70 @@ __global__ void __launch_bounds__(LC_THREADS, 1) k_slab_lc(const SlabArgs a) {
     };
     auto tile_end = [&](int64_t t) __attribute__((always_inline)) {
         const int64_t wrow0 = row_begin + t * LC_TM + wr * RW;
-        if (row_begin + (t + 1) * LC_TM > row_end) {
+        // a row half that starts past the range (the upper half of a partial
+        // last tile) contributes nothing and reads no B: its columns could lie
+        // past the padded row stride of B, which is a multiple of 128 only
+        if (wrow0 < row_end) {
+            if (wrow0 + RW > row_end) {
 #pragma unroll
-            for (int mb = 0; mb < MB; ++mb)
+                for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const bool dead = wrow0 + mb * 16 + TR::acc_row(g, r) >= row_end;
+                    for (int r = 0; r < 4; ++r) {
+                        const bool dead = wrow0 + mb * 16 + TR::acc_row(g, r) >= row_end;
 #pragma unroll
-                    for (int nb = 0; nb < NBW; ++nb)
-                        if (dead) wacc[mb][nb][r] = 0.f;
-                }
+                        for (int nb = 0; nb < NBW; ++nb)
+                            if (dead) wacc[mb][nb][r] = 0.f;
+                    }
+            }
+            // rows past the range in this half contribute zeros; B's padded
+            // columns up to the next multiple of 128 are zeros
+            slab_mode2_pipe<MATH, MB, NBW, JB>(vacc, wacc, a, jbase, wrow0, l16, g);
         }
-        // rows past the range (a partial last tile) contribute zeros; B's
-        // padded columns exist up to ldb, a multiple of 128 >= every row read
-        slab_mode2_grouped<MATH, MB, NBW, JB, (JB > 4 && NBW > 1) ? JB / 2 : JB>(vacc, wacc, a, jbase, wrow0, l16, g);
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
             for (int nb = 0; nb < NBW; ++nb) wacc[mb][nb] = zero_accv<accv_t>();
     };
 
+    // chunk q = t nk + kc: tile t, k-chunk kc.  The copies run ahead of the
+    // work: X two chunks (coordinates tx, kx), C one chunk (kcn).
+    const int nkc = int(nk);
+    int64_t tx = 0;
+    int kx = 0, kcn = 0;
+    auto next_x = [&](uint32_t stage) __attribute__((always_inline)) {
+        if (kx == 0) set_x_offsets(row_begin + tx * LC_TM);
+        copy_x(stage, tx, kx);
+        if (++kx == nkc) { kx = 0; ++tx; }
+    };
+    auto next_c = [&](uint32_t stage) __attribute__((always_inline)) {
+        copy_c(stage, kcn);
+        if (++kcn == nkc) kcn = 0;
+    };
     if (nq > 0) {
-        copy_x(xbuf, 0);
-        copy_c(cbuf, 0);
-        if (nq > 1) copy_x(xbuf + LC_XSTAGE, 1);
+        next_x(xlds);
+        next_c(clds);
+        if (nq > 1) next_x(xlds + LC_XSTAGE);
     }
+    int64_t t = 0;
+    int kc = 0, xst = 0, cst = 0;
     for (int64_t q = 0; q < nq; ++q) {
         // chunk q landed everywhere: this wave's copies of X(q) and C(q) are
         // done when at most its copies of X(q + 1) are outstanding
         if (q + 1 < nq) wait_vmcnt<XOPS>();
         else wait_vmcnt<0>();
         __builtin_amdgcn_s_barrier();
-        const int xst = int(q % 3), cst = int(q & 1);
-        if (q + 1 < nq) copy_c(cbuf + (1 - cst) * CSTAGE, q + 1);
-        if (q + 2 < nq) copy_x(xbuf + ((xst + 2) % 3) * LC_XSTAGE, q + 2);
+        if (q + 1 < nq) next_c(clds + uint32_t((cst ^ 1) * CSTAGE));
+        if (q + 2 < nq) next_x(xlds + uint32_t((xst == 0 ? 2 : xst - 1) * LC_XSTAGE));
         compute(xlds + uint32_t(xst * LC_XSTAGE), clds + uint32_t(cst * CSTAGE));
-        if (q % nk == nk - 1) tile_end(q / nk);
+        if (kc == nkc - 1) {
+            tile_end(t);
+            kc = 0;
+            ++t;
+        } else {
+            ++kc;
+        }
+        xst = xst == 2 ? 0 : xst + 1;
+        cst ^= 1;
     }
 
     // the upper row half adds its V partial to the lower one's through LDS
@@ -1420,7 +1536,8 @@ static int dma_rowbytes(const SlabArgs &a) {
     if (mode == 4) return a.I3 % (256 / es) == 0 ? 1 : 0;   // copy-wave kernel
     if (mode == 0 || mode == 5) {                            // C through LDS where it applies
         if constexpr (WC == 4 && (MATH == M_BF16 || MATH == M_BF16X3) && std::is_same<XT, uint16_t>::value)
-            if (a.I3 % 64 == 0 && a.ldc % 64 == 0 && aligned(a.Chi, 16) && (!a.Clo || aligned(a.Clo, 16)) &&
+            if (a.I3 % 64 == 0 && a.ldc % 64 == 0 && a.I3 <= (int64_t(1) << 22) && a.ldc <= (int64_t(1) << 22) &&
+                aligned(a.Chi, 16) && (!a.Clo || aligned(a.Clo, 16)) &&
                 (mode == 5 || a.rows_per_split >= LC_TM))
                 return 128;
         if (mode == 5) return 0;
