@@ -915,6 +915,29 @@ __device__ __forceinline__ u32x4 lds_read16_at(uint32_t addr) {
     asm volatile("ds_read_b128 %0, %1 offset:%2" : "=v"(v) : "v"(addr), "i"(OFF));
     return v;
 }
+// wait until at most N LDS reads of this wave are in flight
+template <int N>
+__device__ __forceinline__ void lds_wait() {
+    static_assert(N >= 0 && N < 16, "lgkmcnt range");
+    asm volatile("s_waitcnt lgkmcnt(%0)" : : "n"(N));
+}
+// makes r's value available only after the preceding wait (r was written by
+// an LDS read issued through inline assembly)
+__device__ __forceinline__ void lds_dep(u32x4 &r) { asm volatile("" : "+v"(r)); }
+// Read order and waits of one chunk of k_slab_lc: per k-group NC C reads then
+// MB X reads; group g = (kg, mb) needs reads up to need(g); before group g the
+// reads up to issued(g) have been issued, keeping at most 12 in flight past
+// the last read known to have returned.
+template <int NC_, int MB, int NKG>
+struct LcReadSched {
+    static constexpr int NC = NC_, PER_KG = NC_ + MB, NR = NKG * PER_KG;
+    static constexpr int need(int g) { return (g / MB) * PER_KG + NC + g % MB; }
+    static constexpr int issued(int g) {
+        if (g < 0) return 0;
+        const int done = g == 0 ? 0 : need(g - 1) + 1;
+        return done + 12 < NR ? done + 12 : NR;
+    }
+};
 template <typename F, int... I>
 __device__ __forceinline__ void static_for_seq(F &&f, std::integer_sequence<int, I...>) {
     (f(std::integral_constant<int, I>{}), ...);
@@ -1038,35 +1061,46 @@ __global__ void __launch_bounds__(LC_THREADS, 1) k_slab_lc(const SlabArgs a) {
     }
     const uint32_t xlds = lds_offset(xbuf), clds = lds_offset(cbuf);
 
-    // one chunk of matrix-core work: C fragments and the X fragments of
-    // k-group 0 first, those of k-group 1 read while k-group 0 computes
-    auto compute = [&](uint32_t xs, uint32_t cs) __attribute__((always_inline)) {
-        V16 cf[NCF], x0[MB], x1[MB];
-        const uint32_t xa0 = xs + xl[0], xa1 = xs + xl[1];
+    // one chunk of matrix-core work, in groups (k-group kg, 16-row block mb).
+    // The chunk's LDS reads are issued in the order the groups consume them
+    // (per k-group: its C fragments, then the X fragments of blocks 0 .. MB-1)
+    // with at most 12 in flight (the LDS counter counts to 15; 12 keeps the
+    // fragments within the registers at two waves per SIMD), and each group
+    // waits only until its own operands have returned (LDS reads of a wave
+    // return in order): the first products start after a few reads instead of
+    // after all of them.
+    typedef LcReadSched<NCF / NKG, MB, NKG> SC;
+    auto compute = [&](uint32_t xs, uint32_t cs, auto &&after_group) __attribute__((always_inline)) {
+        u32x4 rd[SC::NR];
+        const uint32_t xa[NKG] = {xs + xl[0], xs + xl[1]};
         const uint32_t ca[NKG] = {cs + cl[0], cs + cl[1]};
-        static_for<NKG * NBW>([&](auto i) __attribute__((always_inline)) {
-            constexpr int kg = decltype(i)::value / NBW, nb = decltype(i)::value % NBW;
-            cf[i * (X3 ? 2 : 1)].u = lds_read16_at<nb * 2048>(ca[kg]);
-            if constexpr (X3) cf[i * 2 + 1].u = lds_read16_at<CPART + nb * 2048>(ca[kg]);
-        });
-        static_for<MB>([&](auto m) __attribute__((always_inline)) { x0[m].u = lds_read16_at<decltype(m)::value * 2048>(xa0); });
-        lds_wait_all(cf);
-        lds_wait_all(x0);
-        static_for<MB>([&](auto m) __attribute__((always_inline)) { x1[m].u = lds_read16_at<decltype(m)::value * 2048>(xa1); });
-#pragma unroll
-        for (int kg = 0; kg < NKG; ++kg) {
-            if (kg == 1) lds_wait_all(x1);
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb) {
-                const u32x4 ah = kg == 0 ? x0[mb].u : x1[mb].u;
-#pragma unroll
-                for (int nb = 0; nb < NBW; ++nb) {
-                    const int c = (kg * NBW + nb) * (X3 ? 2 : 1);
-                    wacc[mb][nb] = mfma_bf16(ah, cf[c].u, wacc[mb][nb]);
-                    if constexpr (X3) wacc[mb][nb] = mfma_bf16(ah, cf[c + 1].u, wacc[mb][nb]);
-                }
+        auto issue = [&](auto I) __attribute__((always_inline)) {
+            constexpr int i = decltype(I)::value, kg = i / SC::PER_KG, w = i % SC::PER_KG;
+            if constexpr (w < SC::NC) {
+                constexpr int nb = w / (X3 ? 2 : 1), part = w % (X3 ? 2 : 1);
+                rd[i] = lds_read16_at<part * CPART + nb * 2048>(ca[kg]);
+            } else {
+                rd[i] = lds_read16_at<(w - SC::NC) * 2048>(xa[kg]);
             }
-        }
+        };
+        static_for<NKG * MB>([&](auto G) __attribute__((always_inline)) {
+            constexpr int g = decltype(G)::value, kg = g / MB, mb = g % MB;
+            constexpr int i0 = SC::issued(g - 1), i1 = SC::issued(g);
+            static_for<i1 - i0>([&](auto J) __attribute__((always_inline)) {
+                issue(std::integral_constant<int, i0 + decltype(J)::value>{});
+            });
+            lds_wait<i1 - SC::need(g) - 1>();
+            constexpr int cb = kg * SC::PER_KG, xr = cb + SC::NC + mb;
+            lds_dep(rd[xr]);
+            if constexpr (mb == 0)
+                static_for<SC::NC>([&](auto C) __attribute__((always_inline)) { lds_dep(rd[cb + decltype(C)::value]); });
+#pragma unroll
+            for (int nb = 0; nb < NBW; ++nb) {
+                wacc[mb][nb] = mfma_bf16(rd[xr], rd[cb + nb * (X3 ? 2 : 1)], wacc[mb][nb]);
+                if constexpr (X3) wacc[mb][nb] = mfma_bf16(rd[xr], rd[cb + nb * 2 + 1], wacc[mb][nb]);
+            }
+            after_group(G);
+        });
     };
     auto tile_end = [&](int64_t t) __attribute__((always_inline)) {
         const int64_t wrow0 = row_begin + t * LC_TM + wr * RW;
@@ -1096,23 +1130,29 @@ __global__ void __launch_bounds__(LC_THREADS, 1) k_slab_lc(const SlabArgs a) {
     };
 
     // chunk q = t nk + kc: tile t, k-chunk kc.  The copies run ahead of the
-    // work: X two chunks (coordinates tx, kx), C one chunk (kcn).
+    // work: X two chunks (coordinates tx, kx), C one chunk (kcn).  C's copies
+    // are issued right after the barrier; X's are spread between the
+    // matrix-core groups of the chunk (one after every second group), so that
+    // a wave whose copy waits for room in the memory pipeline has products in
+    // flight.
     const int nkc = int(nk);
     int64_t tx = 0;
     int kx = 0, kcn = 0;
-    auto next_x = [&](uint32_t stage) __attribute__((always_inline)) {
-        if (kx == 0) set_x_offsets(row_begin + tx * LC_TM);
-        copy_x(stage, tx, kx);
-        if (++kx == nkc) { kx = 0; ++tx; }
-    };
     auto next_c = [&](uint32_t stage) __attribute__((always_inline)) {
         copy_c(stage, kcn);
         if (++kcn == nkc) kcn = 0;
     };
+    static_assert(2 * XOPS <= NKG * MB, "one X copy per two groups");
     if (nq > 0) {
-        next_x(xlds);
+        set_x_offsets(row_begin);
+        copy_x(xlds, 0, 0);
         next_c(clds);
-        if (nq > 1) next_x(xlds + LC_XSTAGE);
+        if (nq > 1) {
+            if (nkc == 1) set_x_offsets(row_begin + LC_TM);
+            copy_x(xlds + LC_XSTAGE, nkc == 1 ? 1 : 0, nkc == 1 ? 0 : 1);
+        }
+        tx = nkc <= 2 ? (nkc == 1 ? 2 : 1) : 0;
+        kx = nkc <= 2 ? 0 : 2;
     }
     int64_t t = 0;
     int kc = 0, xst = 0, cst = 0;
@@ -1123,15 +1163,27 @@ __global__ void __launch_bounds__(LC_THREADS, 1) k_slab_lc(const SlabArgs a) {
         else wait_vmcnt<0>();
         __builtin_amdgcn_s_barrier();
         if (q + 1 < nq) next_c(clds + uint32_t((cst ^ 1) * CSTAGE));
-        if (q + 2 < nq) next_x(xlds + uint32_t((xst == 0 ? 2 : xst - 1) * LC_XSTAGE));
-        compute(xlds + uint32_t(xst * LC_XSTAGE), clds + uint32_t(cst * CSTAGE));
-        if (kc == nkc - 1) {
+        const bool x_next = q + 2 < nq, last_of_tile = kc == nkc - 1;
+        const uint32_t xstage = xlds + uint32_t((xst == 0 ? 2 : xst - 1) * LC_XSTAGE);
+        const char *xb = xslab;
+        if (x_next) {
+            if (kx == 0) set_x_offsets(row_begin + tx * LC_TM);
+            xb = xslab + (row_begin + tx * LC_TM) * xrow_bytes + kx * 128;
+        }
+        const uint32_t xs = xlds + uint32_t(xst * LC_XSTAGE), cs = clds + uint32_t(cst * CSTAGE);
+        compute(xs, cs, [&](auto G) __attribute__((always_inline)) {
+            constexpr int g = decltype(G)::value;
+            if constexpr (g % 2 == 1 && g / 2 < XOPS)
+                if (x_next) dma16_to_lds_m0(xb + xlo[g / 2], xstage + uint32_t((wave * XOPS + g / 2) * 1024));
+        });
+        if (last_of_tile) {
             tile_end(t);
             kc = 0;
             ++t;
         } else {
             ++kc;
         }
+        if (x_next && ++kx == nkc) { kx = 0; ++tx; }
         xst = xst == 2 ? 0 : xst + 1;
         cst ^= 1;
     }
