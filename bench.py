@@ -44,13 +44,16 @@ def chain_flops(I, J):
     return 2.0 * (J * I ** 3 + J * J * I * I + J ** 3 * I)
 
 
+# the sources the chain kernels (the slab kernel among them) are built from
+CHAIN_SOURCES = ("ttm_chain.hip", "ttm_device.hpp", "ttm_host.hpp")
+
+
 def kernel_src_sha():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2411_13532_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(f.read())
+    for name in CHAIN_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
