@@ -31,9 +31,16 @@ struct BwdPlan {
     bool need_w, need_v, need_h, need_r;
     size_t off_W, off_V, off_H, off_R, off_P, total;
     int64_t part_elems;
+    // float32 with J3 <= 32 (a multiple of 4) and I3 a multiple of 64: the
+    // X-sized products (W, dX, dC) run on the streaming kernels below
+    bool skinny;
+    int dc_splits;
+    int64_t dc_rows;
 };
 
 constexpr int64_t KT_F32 = 32, KT_F64 = 16;
+// partials per group of the first stage of the two-level split sums
+constexpr int SUM_GROUP = 16;
 
 struct SplitK {
     int ks;
@@ -73,9 +80,20 @@ void make_bwd_plan(const ttm_shape &s, int math, bool dX, bool dA, bool dB, bool
         SplitK k = choose_split(p.J2, p.I2, p.I1 * p.J3, 1, KT);
         if (k.ks > 1) p.part_elems = std::max(p.part_elems, int64_t(k.ks) * p.J2 * p.I2);
     }
+    const int64_t M = p.I1 * p.I2;
+    p.skinny = math == TTM_MATH_F32 && p.J3 <= 32 && p.J3 % 4 == 0 && p.I3 % 64 == 0 && M < (int64_t(1) << 31) &&
+               p.I3 < (int64_t(1) << 24);
     if (dC) {
         SplitK k = choose_split(p.J3, p.I3, p.I1 * p.I2, 1, KT);
         if (k.ks > 1) p.part_elems = std::max(p.part_elems, int64_t(k.ks) * p.J3 * p.I3);
+        if (p.skinny) {
+            const int64_t s0 = std::min<int64_t>(512, ceil_div(M, 64));
+            p.dc_rows = round_up(ceil_div(M, s0), 4);
+            p.dc_splits = int(ceil_div(M, p.dc_rows));
+            // the partials, then their group sums
+            p.part_elems =
+                std::max(p.part_elems, (int64_t(p.dc_splits) + ceil_div(p.dc_splits, SUM_GROUP)) * p.J3 * p.I3);
+        }
     }
     size_t off = 0;
     auto take = [&](bool need, int64_t elems) -> size_t {
@@ -97,6 +115,200 @@ GemmArgs gargs() {
     memset(&a, 0, sizeof a);
     a.P = 1;
     return a;
+}
+
+// ---------------------------------------------------------------------------
+// Streaming kernels for the three products of the adjoint that read or write
+// an X-sized tensor, in float32 with J3 <= 32 (a multiple of 4) and I3 a
+// multiple of 64.  Rows r = (i1, i2) of X, dX (I3 long) and of W, R (J3 long).
+// Each lane reads 16 bytes of the X-sized operand (or writes them, for dX)
+// straight into a 16 x 16 x 4 matrix-core operand: which k (or n) value a
+// (lane group, element) slot carries is free as long as both operands agree,
+// so one 16-byte access feeds four products.  No LDS, no barriers; the small
+// operands (C, R) come through the caches.
+// ---------------------------------------------------------------------------
+constexpr int SK_WAVES = 4;
+
+// W[r][j] = sum_k X[r][k] C[j][k].  A wave owns 32 rows (two 16-row blocks)
+// and all 32 columns; k slot (g, s) of chunk k0 carries k = k0 + 4 g + s.
+__global__ void __launch_bounds__(64 * SK_WAVES) k_bwd_w_f32(const float *__restrict__ X, const float *__restrict__ C,
+                                                            float *__restrict__ W, int64_t M, int I3, int J3) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l16 = lane & 15, g = lane >> 4;
+    const int64_t r0 = (int64_t(blockIdx.x) * SK_WAVES + wave) * 32;
+    if (r0 >= M) return;
+    const float *xr[2];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) {
+        const int64_t row = r0 + mb * 16 + l16;
+        xr[mb] = X + (row < M ? row : M - 1) * I3 + 4 * g;
+    }
+    const bool cv[2] = {l16 < J3, 16 + l16 < J3};
+    const float *cr[2] = {C + int64_t(cv[0] ? l16 : 0) * I3 + 4 * g, C + int64_t(cv[1] ? 16 + l16 : 0) * I3 + 4 * g};
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) acc[mb][nb] = zero_accv<f32x4>();
+    for (int k0 = 0; k0 < I3; k0 += 64) {
+        V16 xa[2][4], cb[2][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb) xa[mb][u] = ld16(xr[mb] + k0 + 16 * u);
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) {
+                cb[nb][u] = ld16(cr[nb] + k0 + 16 * u);
+                if (!cv[nb]) cb[nb][u] = zero16();
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                    for (int nb = 0; nb < 2; ++nb) acc[mb][nb] = mfma_f32(xa[mb][u].f[e], cb[nb][u].f[e], acc[mb][nb]);
+    }
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int64_t row = r0 + mb * 16 + 4 * g + rr;
+            if (row >= M) continue;
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb)
+                if (cv[nb]) W[row * J3 + nb * 16 + l16] = acc[mb][nb][rr];
+        }
+}
+
+// part[s][j][i] = sum_{r in split s} R[r][j] X[r][i].  grid (splits,
+// ceil(I3 / 256)); a wave owns 64 columns i; k slot g of a step carries row
+// r0 + g, and column n of product e is i = i0 + 4 n + e.
+__global__ void __launch_bounds__(64 * SK_WAVES) k_bwd_dc_f32(const float *__restrict__ R, const float *__restrict__ X,
+                                                             float *__restrict__ part, int64_t M, int I3, int J3,
+                                                             int64_t rows_per_split) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l16 = lane & 15, g = lane >> 4;
+    const int i0 = (blockIdx.y * SK_WAVES + wave) * 64;
+    if (i0 >= I3) return;
+    const int64_t rb = int64_t(blockIdx.x) * rows_per_split;
+    const int64_t re = M < rb + rows_per_split ? M : rb + rows_per_split;
+    const bool jv[2] = {l16 < J3, 16 + l16 < J3};
+    f32x4 acc[2][4];
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[jb][e] = zero_accv<f32x4>();
+    for (int64_t r0 = rb; r0 < re; r0 += 16) {
+        V16 xb[4];
+        float ra[4][2];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t row = r0 + 4 * u + g;
+            const bool ok = row < re;
+            const int64_t rc = ok ? row : rb;
+            xb[u] = ld16(X + rc * I3 + i0 + 4 * l16);
+#pragma unroll
+            for (int jb = 0; jb < 2; ++jb) {
+                const float v = R[rc * J3 + (jv[jb] ? jb * 16 + l16 : 0)];
+                ra[u][jb] = ok && jv[jb] ? v : 0.f;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int jb = 0; jb < 2; ++jb) acc[jb][e] = mfma_f32(ra[u][jb], xb[u].f[e], acc[jb][e]);
+    }
+    float *pp = part + int64_t(blockIdx.x) * J3 * I3;
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int j = jb * 16 + 4 * g + rr;
+            if (j >= J3) continue;
+            const f32x4 v = {acc[jb][0][rr], acc[jb][1][rr], acc[jb][2][rr], acc[jb][3][rr]};
+            *reinterpret_cast<f32x4 *>(pp + int64_t(j) * I3 + i0 + 4 * l16) = v;
+        }
+}
+
+// dX[r][i] = sum_j R[r][j] C[j][i].  grid (ceil(M / DX_ROWS), ceil(I3 /
+// 256)); a wave owns 64 columns i and keeps their C fragments in
+// registers; k slot (g, e) of half h carries j = 16 h + 4 g + e, column n of
+// output product t is i = i0 + 4 n + t, so each lane stores 16 bytes per row.
+constexpr int DX_ROWS = 64;
+__global__ void __launch_bounds__(64 * SK_WAVES) k_bwd_dx_f32(const float *__restrict__ R, const float *__restrict__ C,
+                                                             float *__restrict__ dX, int64_t M, int I3, int J3) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l16 = lane & 15, g = lane >> 4;
+    const int i0 = (blockIdx.y * SK_WAVES + wave) * 64;
+    if (i0 >= I3) return;
+    const int64_t rb = int64_t(blockIdx.x) * DX_ROWS;
+    const int64_t re = M < rb + DX_ROWS ? M : rb + DX_ROWS;
+    V16 cf[2][4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int j = 16 * h + 4 * g + e;
+            cf[h][e] = ld16(C + int64_t(j < J3 ? j : 0) * I3 + i0 + 4 * l16);
+            if (j >= J3) cf[h][e] = zero16();
+        }
+    const bool hv[2] = {4 * g < J3, 16 + 4 * g < J3};
+    // the R fragments of all DX_ROWS rows are loaded first
+    V16 ra[DX_ROWS / 16][2];
+#pragma unroll
+    for (int q = 0; q < DX_ROWS / 16; ++q) {
+        const int64_t row = rb + 16 * q + l16;
+        const int64_t rc = row < re ? row : re - 1;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            ra[q][h] = ld16(R + rc * J3 + (hv[h] ? 16 * h + 4 * g : 0));
+            if (!hv[h]) ra[q][h] = zero16();
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < DX_ROWS / 16; ++q) {
+        const int64_t r0 = rb + 16 * q;
+        if (r0 >= re) break;
+        f32x4 acc[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = zero_accv<f32x4>();
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) acc[t] = mfma_f32(ra[q][h].f[e], cf[h][e].f[t], acc[t]);
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int64_t r = r0 + 4 * g + rr;
+            if (r >= re) continue;
+            const f32x4 v = {acc[0][rr], acc[1][rr], acc[2][rr], acc[3][rr]};
+            *reinterpret_cast<f32x4 *>(dX + r * I3 + i0 + 4 * l16) = v;
+        }
+    }
+}
+
+// First stage of a two-level fixed-order sum of S partials of n elements:
+// out[b][e] = sum_{s < G, b G + s < S} part[(b G + s) * n + e], increasing s;
+// grid (ceil(n / 256), ceil(S / G)).
+__global__ void __launch_bounds__(256) k_sum_groups_f32(const float *__restrict__ part, int64_t n, int S,
+                                                       float *__restrict__ out) {
+    const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (e >= n) return;
+    const int s0 = blockIdx.y * SUM_GROUP;
+    const int cnt = S - s0 < SUM_GROUP ? S - s0 : SUM_GROUP;
+    float v[SUM_GROUP];
+#pragma unroll
+    for (int s = 0; s < SUM_GROUP; ++s) {
+        const float x = part[int64_t(s0 + (s < cnt ? s : 0)) * n + e];
+        v[s] = s < cnt ? x : 0.f;
+    }
+    float acc = 0.f;
+#pragma unroll
+    for (int s = 0; s < SUM_GROUP; ++s) acc += v[s];
+    out[int64_t(blockIdx.y) * n + e] = acc;
 }
 
 template <int MATH>
@@ -151,6 +363,8 @@ int run_backward(const BwdPlan &p, const void *G, const void *X, const void *A, 
                  void *dX, void *dA, void *dB, void *dC, unsigned char *ws, hipStream_t st) {
     void *W = ws + p.off_W, *V = ws + p.off_V, *H = ws + p.off_H, *R = ws + p.off_R, *Pt = ws + p.off_P;
     const int64_t I1 = p.I1, I2 = p.I2, I3 = p.I3, J1 = p.J1, J2 = p.J2, J3 = p.J3, NN = p.NN;
+    // the streaming kernels read X and C 16 bytes at a time
+    const bool skinny = p.skinny && aligned(X, 16) && aligned(C, 16);
     int rc = TTM_OK;
     if (p.need_w) {   // W[(i1,i2)][j3] = sum_i3 X[(i1,i2)][i3] C[j3][i3]
         GemmArgs a = gargs();
@@ -159,7 +373,17 @@ int run_backward(const BwdPlan &p, const void *G, const void *X, const void *A, 
         a.sam = I3; a.saki = 1;
         a.sbn = I3; a.sbki = 1;
         a.scm = J3; a.scn = 1;
-        if ((rc = run_gemm<MATH>(a, 1, false, nullptr, st, "ttm_bwd_W"))) return rc;
+        if (MATH == M_F32 && skinny) {
+            const int64_t M = I1 * I2;
+            rc = launch("ttm_bwd_W", st, [&] {
+                hipLaunchKernelGGL(k_bwd_w_f32, dim3(unsigned(ceil_div(M, 32 * SK_WAVES))), dim3(64 * SK_WAVES), 0, st,
+                                   static_cast<const float *>(X), static_cast<const float *>(C), static_cast<float *>(W),
+                                   M, int(I3), int(J3));
+            });
+            if (rc) return rc;
+        } else if ((rc = run_gemm<MATH>(a, 1, false, nullptr, st, "ttm_bwd_W"))) {
+            return rc;
+        }
     }
     if (p.need_v) {   // V[i1][j2][j3] = sum_i2 B[j2][i2] W[i1][i2][j3]
         GemmArgs a = gargs();
@@ -204,7 +428,17 @@ int run_backward(const BwdPlan &p, const void *G, const void *X, const void *A, 
         a.sam = J3; a.saki = 1;
         a.sbn = 1; a.sbki = I3;
         a.scm = I3; a.scn = 1;
-        if ((rc = run_gemm<MATH>(a, 1, false, nullptr, st, "ttm_bwd_dX"))) return rc;
+        if (MATH == M_F32 && skinny && aligned(dX, 16)) {
+            const int64_t M = I1 * I2;
+            rc = launch("ttm_bwd_dX", st, [&] {
+                hipLaunchKernelGGL(k_bwd_dx_f32, dim3(unsigned(ceil_div(M, DX_ROWS)), unsigned(ceil_div(I3, 64 * SK_WAVES))),
+                                   dim3(64 * SK_WAVES), 0, st, static_cast<const float *>(R),
+                                   static_cast<const float *>(C), static_cast<float *>(dX), M, int(I3), int(J3));
+            });
+            if (rc) return rc;
+        } else if ((rc = run_gemm<MATH>(a, 1, false, nullptr, st, "ttm_bwd_dX"))) {
+            return rc;
+        }
     }
     if (dB) {         // dB[j2][i2] = sum_{i1,j3} H[i1][j2][j3] W[i1][i2][j3]
         GemmArgs a = gargs();
@@ -222,7 +456,33 @@ int run_backward(const BwdPlan &p, const void *G, const void *X, const void *A, 
         a.sam = 1; a.saki = J3;
         a.sbn = 1; a.sbki = I3;
         a.scm = I3; a.scn = 1;
-        if ((rc = run_gemm<MATH>(a, 1, true, Pt, st, "ttm_bwd_dC"))) return rc;
+        if (MATH == M_F32 && skinny) {
+            const int64_t M = I1 * I2, n = J3 * I3;
+            rc = launch("ttm_bwd_dC", st, [&] {
+                hipLaunchKernelGGL(k_bwd_dc_f32, dim3(unsigned(p.dc_splits), unsigned(ceil_div(I3, 64 * SK_WAVES))),
+                                   dim3(64 * SK_WAVES), 0, st, static_cast<const float *>(R),
+                                   static_cast<const float *>(X), static_cast<float *>(Pt), M, int(I3), int(J3),
+                                   p.dc_rows);
+            });
+            if (rc) return rc;
+            // partials summed in groups of SUM_GROUP (in order), then the
+            // group sums in order; the group sums go after the partials
+            const int ng = int(ceil_div(p.dc_splits, SUM_GROUP));
+            float *Pg = static_cast<float *>(Pt) + int64_t(p.dc_splits) * n;
+            rc = launch("ttm_bwd_sum_splits", st, [&] {
+                hipLaunchKernelGGL(k_sum_groups_f32, dim3(unsigned(ceil_div(n, 256)), unsigned(ng)), dim3(256), 0, st,
+                                   static_cast<const float *>(Pt), n, p.dc_splits, Pg);
+            });
+            if (rc) return rc;
+            dim3 rg(unsigned(std::min<int64_t>(ceil_div(n, 256), 4096)));
+            rc = launch("ttm_bwd_sum_splits", st, [&] {
+                hipLaunchKernelGGL(k_sum_splits<float>, rg, dim3(256), 0, st, static_cast<const float *>(Pg), n, ng,
+                                   n, static_cast<float *>(dC));
+            });
+            if (rc) return rc;
+        } else if ((rc = run_gemm<MATH>(a, 1, true, Pt, st, "ttm_bwd_dC"))) {
+            return rc;
+        }
     }
     return rc;
 }
