@@ -1346,9 +1346,26 @@ __global__ void __launch_bounds__(256) k_mode1(const Mode1Args a) {
 #pragma unroll
         for (int j = 0; j < NW; ++j) acc[i][j] = zero_accv<accv_t>();
 
+    // A's fragments of a chunk are loaded one chunk ahead and before the next
+    // chunk's V prefetch: vector-memory loads complete in order, so a wait for
+    // A issued after the prefetch would also wait for the prefetch's HBM trip
+    V16 fah[MW][2], fal[MW][2];
+    auto load_a = [&](int64_t ch) __attribute__((always_inline)) {
+#pragma unroll
+        for (int kg = 0; kg < 2; ++kg) {
+            const int64_t k0 = kb + ch * KT + kg * KG + g * VE;
+#pragma unroll
+            for (int i = 0; i < MW; ++i) {
+                const int64_t off = (m0 + (mbase + i) * 16 + l16) * a.lda + k0;
+                fah[i][kg] = ld16(Ah + off);
+                if constexpr (CF::SPLIT) fal[i][kg] = ld16(Al + off);
+            }
+        }
+    };
     if (nch > 0) {
         fetch(0);
         store(0);
+        load_a(0);
     }
     __syncthreads();
     for (int64_t ch = 0; ch < nch; ++ch) {
@@ -1363,13 +1380,11 @@ __global__ void __launch_bounds__(256) k_mode1(const Mode1Args a) {
                 bh[j].u = *reinterpret_cast<const u32x4 *>(lhi + loff);
                 if constexpr (CF::SPLIT) bl[j].u = *reinterpret_cast<const u32x4 *>(llo + loff);
             }
-            const int64_t k0 = kb + ch * KT + kg * KG + g * VE;
 #pragma unroll
             for (int i = 0; i < MW; ++i) {
-                const int64_t off = (m0 + (mbase + i) * 16 + l16) * a.lda + k0;
-                const V16 ah = ld16(Ah + off);
+                const V16 ah = fah[i][kg];
                 V16 al;
-                if constexpr (CF::SPLIT) al = ld16(Al + off);
+                if constexpr (CF::SPLIT) al = fal[i][kg];
 #pragma unroll
                 for (int j = 0; j < NW; ++j) {
                     mma_kgroup<MATH == M_BF16X3 ? M_BF16 : MATH>(acc[i][j], ah, bh[j]);
@@ -1380,7 +1395,10 @@ __global__ void __launch_bounds__(256) k_mode1(const Mode1Args a) {
                 }
             }
         }
-        if (ch + 1 < nch) store(buf ^ 1);
+        if (ch + 1 < nch) {
+            store(buf ^ 1);
+            load_a(ch + 1);
+        }
         __syncthreads();
     }
 
