@@ -34,6 +34,7 @@ struct BwdPlan {
     // float32 with J3 <= 32 (a multiple of 4) and I3 a multiple of 64: the
     // X-sized products (W, dX, dC) run on the streaming kernels below
     bool skinny;
+    bool skinny_vr;   // also J2 <= 32 and I2 a multiple of 64: V and R on streaming kernels
     int dc_splits;
     int64_t dc_rows;
 };
@@ -83,6 +84,7 @@ void make_bwd_plan(const ttm_shape &s, int math, bool dX, bool dA, bool dB, bool
     const int64_t M = p.I1 * p.I2;
     p.skinny = math == TTM_MATH_F32 && p.J3 <= 32 && p.J3 % 4 == 0 && p.I3 % 64 == 0 && M < (int64_t(1) << 31) &&
                p.I3 < (int64_t(1) << 24);
+    p.skinny_vr = p.skinny && p.J2 <= 32 && p.I2 % 64 == 0 && p.I2 < (int64_t(1) << 24) && p.I1 < (int64_t(1) << 31);
     if (dC) {
         SplitK k = choose_split(p.J3, p.I3, p.I1 * p.I2, 1, KT);
         if (k.ks > 1) p.part_elems = std::max(p.part_elems, int64_t(k.ks) * p.J3 * p.I3);
@@ -290,6 +292,132 @@ __global__ void __launch_bounds__(64 * SK_WAVES) k_bwd_dx_f32(const float *__res
     }
 }
 
+// V[i1][j2][j3] = sum_i2 B[j2][i2] W[i1][i2][j3] (J2, J3 <= 32, I2 a
+// multiple of 64).  A workgroup owns one i1; its four waves split the i2
+// range into quarters and add their 32 x 32 partials through LDS in a fixed
+// order.  k slot (g, e) of chunk k0 carries i2 = k0 + 4 g + e: B is read 16
+// bytes per lane, W one float per lane (16 consecutive j3 of a row).
+__global__ void __launch_bounds__(64 * SK_WAVES) k_bwd_v_f32(const float *__restrict__ B, const float *__restrict__ W,
+                                                            float *__restrict__ V, int64_t I1, int I2, int J2,
+                                                            int J3) {
+    __shared__ float red[SK_WAVES - 1][32 * 32];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l16 = lane & 15, g = lane >> 4;
+    const int64_t i1 = blockIdx.x;
+    const int q = I2 / SK_WAVES, kb = wave * q;
+    const bool bv[2] = {l16 < J2, 16 + l16 < J2}, wv[2] = {l16 < J3, 16 + l16 < J3};
+    const float *brow[2] = {B + int64_t(bv[0] ? l16 : 0) * I2 + 4 * g, B + int64_t(bv[1] ? 16 + l16 : 0) * I2 + 4 * g};
+    const float *wcol[2] = {W + i1 * I2 * J3 + (wv[0] ? l16 : 0), W + i1 * I2 * J3 + (wv[1] ? 16 + l16 : 0)};
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) acc[jb][nb] = zero_accv<f32x4>();
+    for (int k0 = kb; k0 < kb + q; k0 += 16) {
+        V16 ba[2];
+        float wb[2][4];
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb) {
+            ba[jb] = ld16(brow[jb] + k0);
+            if (!bv[jb]) ba[jb] = zero16();
+        }
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float x = wcol[nb][int64_t(k0 + 4 * g + e) * J3];
+                wb[nb][e] = wv[nb] ? x : 0.f;
+            }
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+                for (int nb = 0; nb < 2; ++nb) acc[jb][nb] = mfma_f32(ba[jb].f[e], wb[nb][e], acc[jb][nb]);
+    }
+    // element (jb, nb, rr) of a lane: j2 = 16 jb + 4 g + rr, j3 = 16 nb + l16
+    if (wave > 0) {
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) red[wave - 1][((jb * 2 + nb) * 4 + rr) * 64 + lane] = acc[jb][nb][rr];
+    }
+    __syncthreads();
+    if (wave > 0) return;
+#pragma unroll
+    for (int w = 0; w < SK_WAVES - 1; ++w)
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) acc[jb][nb][rr] += red[w][((jb * 2 + nb) * 4 + rr) * 64 + lane];
+    float *Vp = V + i1 * J2 * J3;
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int j2 = 16 * jb + 4 * g + rr;
+            if (j2 >= J2) continue;
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb)
+                if (wv[nb]) Vp[j2 * J3 + 16 * nb + l16] = acc[jb][nb][rr];
+        }
+}
+
+// R[i1][i2][j3] = sum_j2 B[j2][i2] H[i1][j2][j3] (J2, J3 <= 32).  A wave owns
+// 64 rows i2 of one i1 (grid (I1, ceil(I2 / 256))); k slot g of step s
+// carries j2 = 4 s + g; B and H are read one float per lane (16 consecutive
+// i2 or j3), R written 64 contiguous bytes per row and 16 lanes.
+__global__ void __launch_bounds__(64 * SK_WAVES) k_bwd_r_f32(const float *__restrict__ B, const float *__restrict__ H,
+                                                            float *__restrict__ R, int64_t I1, int I2, int J2,
+                                                            int J3) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l16 = lane & 15, g = lane >> 4;
+    const int64_t i1 = blockIdx.x;
+    const int m0 = (blockIdx.y * SK_WAVES + wave) * 64;
+    if (m0 >= I2) return;
+    const bool nv[2] = {l16 < J3, 16 + l16 < J3};
+    const float *Hp = H + i1 * J2 * J3;
+    f32x4 acc[4][2];
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) acc[mb][nb] = zero_accv<f32x4>();
+    for (int s = 0; 4 * s < J2; ++s) {
+        const int j2 = 4 * s + g;
+        const bool kv = j2 < J2;
+        const int j2c = kv ? j2 : 0;
+        float a[4], h[2];
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) {
+            const int i2 = m0 + 16 * mb + l16;
+            const float x = B[int64_t(j2c) * I2 + (i2 < I2 ? i2 : I2 - 1)];
+            a[mb] = kv && i2 < I2 ? x : 0.f;
+        }
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+            const float x = Hp[j2c * J3 + (nv[nb] ? 16 * nb + l16 : 0)];
+            h[nb] = kv && nv[nb] ? x : 0.f;
+        }
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) acc[mb][nb] = mfma_f32(a[mb], h[nb], acc[mb][nb]);
+    }
+    float *Rp = R + i1 * int64_t(I2) * J3;
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int i2 = m0 + 16 * mb + 4 * g + rr;
+            if (i2 >= I2) continue;
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb)
+                if (nv[nb]) Rp[int64_t(i2) * J3 + 16 * nb + l16] = acc[mb][nb][rr];
+        }
+}
+
 // First stage of a two-level fixed-order sum of S partials of n elements:
 // out[b][e] = sum_{s < G, b G + s < S} part[(b G + s) * n + e], increasing s;
 // grid (ceil(n / 256), ceil(S / G)).
@@ -392,7 +520,16 @@ int run_backward(const BwdPlan &p, const void *G, const void *X, const void *A, 
         a.sam = I2; a.saki = 1;
         a.sbb = I2 * J3; a.sbki = J3; a.sbn = 1;
         a.scb = NN; a.scm = J3; a.scn = 1;
-        if ((rc = run_gemm<MATH>(a, I1, false, nullptr, st, "ttm_bwd_V"))) return rc;
+        if (MATH == M_F32 && p.skinny_vr && aligned(B, 16)) {
+            rc = launch("ttm_bwd_V", st, [&] {
+                hipLaunchKernelGGL(k_bwd_v_f32, dim3(unsigned(I1)), dim3(64 * SK_WAVES), 0, st,
+                                   static_cast<const float *>(B), static_cast<const float *>(W), static_cast<float *>(V),
+                                   I1, int(I2), int(J2), int(J3));
+            });
+            if (rc) return rc;
+        } else if ((rc = run_gemm<MATH>(a, I1, false, nullptr, st, "ttm_bwd_V"))) {
+            return rc;
+        }
     }
     if (dA) {         // dA[j1][i1] = sum_n G[j1][n] V[i1][n]
         GemmArgs a = gargs();
@@ -419,7 +556,17 @@ int run_backward(const BwdPlan &p, const void *G, const void *X, const void *A, 
         a.sam = 1; a.saki = I2;
         a.sbb = NN; a.sbki = J3; a.sbn = 1;
         a.scb = I2 * J3; a.scm = J3; a.scn = 1;
-        if ((rc = run_gemm<MATH>(a, I1, false, nullptr, st, "ttm_bwd_R"))) return rc;
+        if (MATH == M_F32 && p.skinny_vr) {
+            rc = launch("ttm_bwd_R", st, [&] {
+                hipLaunchKernelGGL(k_bwd_r_f32, dim3(unsigned(I1), unsigned(ceil_div(I2, 64 * SK_WAVES))),
+                                   dim3(64 * SK_WAVES), 0, st, static_cast<const float *>(B),
+                                   static_cast<const float *>(H), static_cast<float *>(R), I1, int(I2), int(J2),
+                                   int(J3));
+            });
+            if (rc) return rc;
+        } else if ((rc = run_gemm<MATH>(a, I1, false, nullptr, st, "ttm_bwd_R"))) {
+            return rc;
+        }
     }
     if (dX) {         // dX[(i1,i2)][i3] = sum_j3 R[(i1,i2)][j3] C[j3][i3]
         GemmArgs a = gargs();

@@ -248,6 +248,140 @@ __global__ void __launch_bounds__(256) k_compact_rows(const CompactArgs a, const
     }
 }
 
+// The same sweeps for n a multiple of RT (every tile whole): the next tile
+// and its halo are loaded into registers while the current one is computed,
+// and the RT steps of a tile are unrolled with the tile's coefficients read
+// before the recurrence starts.
+template <typename T>
+__global__ void __launch_bounds__(256) k_compact_rows_full(const CompactArgs a, const T *__restrict__ X,
+                                                           T *__restrict__ Y, const T *__restrict__ ws) {
+    typedef RowsCfg<T> CF;
+    constexpr int VE = CF::VE, RT = CF::RT, LD = CF::LD, WPR = CF::WPR, RPP = 64 / WPR;
+    extern __shared__ __align__(16) unsigned char smem_rows[];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    T *tin = reinterpret_cast<T *>(smem_rows) + wave * CF::WAVE_ELEMS;
+    T *tout = tin + 64 * LD;
+    const int64_t n = a.n, ntiles = n / RT;
+    const int64_t row0 = (int64_t(blockIdx.x) * (blockDim.x >> 6) + wave) * 64;
+    if (row0 >= a.nfib) return;                       // whole wave: no LDS shared across waves
+    const int nrows = int(a.nfib - row0 < 64 ? a.nfib - row0 : 64);
+    const T *inv = ws, *cp = ws + n, *w = ws + 2 * n, *z = ws + 3 * n;
+    const T kk = ws[4 * n], ag = ws[4 * n + 1];
+    const T ca = T(a.ca), cb = T(a.cb), alpha = T(a.alpha);
+    const int64_t myrow = row0 + (lane < nrows ? lane : nrows - 1);
+    const T *urow = X + myrow * n;
+
+    // lane l moves word l % WPR of rows l / WPR + RPP i (rows past the range
+    // re-read the last row and are not stored); halo values: lane l holds
+    // point t0 + RT + (l & 1) (mod n) of row l / 2 and of row 32 + l / 2
+    const int wl = lane % WPR, rl = lane / WPR;
+    V16 buf[WPR];
+    T halo[2];
+    auto rowc = [&](int r) -> int64_t { return row0 + (r < nrows ? r : nrows - 1); };
+    auto fetch = [&](const T *src, int64_t t0, bool with_halo) __attribute__((always_inline)) {
+#pragma unroll
+        for (int i = 0; i < WPR; ++i) buf[i] = ld16(src + rowc(rl + RPP * i) * n + t0 + wl * VE);
+        if (with_halo) {
+            int64_t c = t0 + RT + (lane & 1);
+            if (c >= n) c -= n;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) halo[h] = src[rowc(32 * h + (lane >> 1)) * n + c];
+        }
+    };
+    auto put = [&](bool with_halo) __attribute__((always_inline)) {
+#pragma unroll
+        for (int i = 0; i < WPR; ++i) {
+            const int r = rl + RPP * i;
+#pragma unroll
+            for (int e = 0; e < VE; ++e) tin[r * LD + wl * VE + e] = reinterpret_cast<const T *>(&buf[i])[e];
+        }
+        if (with_halo) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) tin[(32 * h + (lane >> 1)) * LD + RT + (lane & 1)] = halo[h];
+        }
+    };
+    auto store_tile = [&](int64_t t0) __attribute__((always_inline)) {
+#pragma unroll
+        for (int i = 0; i < WPR; ++i) {
+            const int r = rl + RPP * i;
+            if (r < nrows) {
+                V16 v;
+#pragma unroll
+                for (int e = 0; e < VE; ++e) reinterpret_cast<T *>(&v)[e] = tout[r * LD + wl * VE + e];
+                *reinterpret_cast<u32x4 *>(Y + (row0 + r) * n + t0 + wl * VE) = v.u;
+            }
+        }
+    };
+
+    // forward sweep
+    T um2 = urow[n - 2], um1 = urow[n - 1], uc = urow[0], up1 = urow[1];
+    T yp = T(0), acc = T(0);
+    fetch(X, 0, true);
+    for (int64_t t = 0; t < ntiles; ++t) {
+        const int64_t t0 = t * RT;
+        wave_sync();
+        put(true);
+        wave_sync();
+        T u[RT + 2];
+        const T *mine = tin + lane * LD;
+#pragma unroll
+        for (int c = 0; c < RT + 2; ++c) u[c] = mine[c];
+        if (t + 1 < ntiles) fetch(X, t0 + RT, true);
+        T ci[RT], cw[RT];
+#pragma unroll
+        for (int c = 0; c < RT; ++c) {
+            ci[c] = inv[t0 + c];
+            cw[c] = w[t0 + c];
+        }
+#pragma unroll
+        for (int c = 0; c < RT; ++c) {
+            const T up2 = u[c + 2];
+            const T d = ca * (up1 - um1) + cb * (up2 - um2);
+            yp = (d - alpha * yp) * ci[c];
+            tout[lane * LD + c] = yp;
+            acc += cw[c] * yp;
+            um2 = um1;
+            um1 = uc;
+            uc = up1;
+            up1 = up2;
+        }
+        wave_sync();
+        store_tile(t0);
+    }
+    const T sc = kk * (acc + ag * yp);
+
+    // backward sweep over the same tiles in reverse, in place in Y (the
+    // forward's stores by other lanes of this wave are complete first)
+    T yn = T(0);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    fetch(Y, (ntiles - 1) * RT, false);
+    for (int64_t t = ntiles - 1; t >= 0; --t) {
+        const int64_t t0 = t * RT;
+        wave_sync();
+        put(false);
+        wave_sync();
+        T v[RT];
+        const T *mine = tin + lane * LD;
+#pragma unroll
+        for (int c = 0; c < RT; ++c) v[c] = mine[c];
+        if (t > 0) fetch(Y, t0 - RT, false);
+        T cc[RT], cz[RT];
+#pragma unroll
+        for (int c = 0; c < RT; ++c) {
+            cc[c] = t0 + c == n - 1 ? T(0) : cp[t0 + c];
+            cz[c] = z[t0 + c];
+        }
+#pragma unroll
+        for (int c = RT - 1; c >= 0; --c) {
+            yn = v[c] - cc[c] * yn;
+            tout[lane * LD + c] = yn - sc * cz[c];
+        }
+        wave_sync();
+        store_tile(t0);
+    }
+}
+
 }  // namespace
 
 }  // namespace ttm
@@ -313,17 +447,22 @@ int ttm_compact_apply(const int64_t *dims, int mode, const void *X, void *Y, int
             prep_attr[k] = true;
         }
     }
+    // mode 3: whole tiles take the prefetching kernel
+    const bool full_tiles = n % (dtype == TTM_F64 ? RowsCfg<double>::RT : RowsCfg<float>::RT) == 0;
     if (mode == 3) {
-        static bool attr_set[2] = {false, false};
-        const int k = dtype == TTM_F64 ? 0 : 1;
-        if (!attr_set[k]) {
-            const void *fn = dtype == TTM_F64 ? reinterpret_cast<const void *>(&k_compact_rows<double>)
-                                              : reinterpret_cast<const void *>(&k_compact_rows<float>);
+        static bool attr_set[2][2] = {{false, false}, {false, false}};
+        const int k = dtype == TTM_F64 ? 0 : 1, f = full_tiles ? 1 : 0;
+        if (!attr_set[k][f]) {
+            const void *fn = dtype == TTM_F64
+                                 ? (full_tiles ? reinterpret_cast<const void *>(&k_compact_rows_full<double>)
+                                               : reinterpret_cast<const void *>(&k_compact_rows<double>))
+                                 : (full_tiles ? reinterpret_cast<const void *>(&k_compact_rows_full<float>)
+                                               : reinterpret_cast<const void *>(&k_compact_rows<float>));
             const int bytes = dtype == TTM_F64 ? int(4 * RowsCfg<double>::WAVE_ELEMS * sizeof(double))
                                                : int(4 * RowsCfg<float>::WAVE_ELEMS * sizeof(float));
             if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess)
                 return TTM_ERR_HIP;
-            attr_set[k] = true;
+            attr_set[k][f] = true;
         }
     }
     int rc = TTM_OK;
@@ -335,7 +474,7 @@ int ttm_compact_apply(const int64_t *dims, int mode, const void *X, void *Y, int
             });
         if (rc == TTM_OK && mode == 3)
             rc = launch("ttm_compact", st, [&] {
-                hipLaunchKernelGGL(k_compact_rows<double>, dim3(row_blocks), dim3(256),
+                hipLaunchKernelGGL(full_tiles ? k_compact_rows_full<double> : k_compact_rows<double>, dim3(row_blocks), dim3(256),
                                    4 * RowsCfg<double>::WAVE_ELEMS * sizeof(double), st, a,
                                    static_cast<const double *>(X), static_cast<double *>(Y),
                                    static_cast<const double *>(ws));
@@ -353,7 +492,7 @@ int ttm_compact_apply(const int64_t *dims, int mode, const void *X, void *Y, int
             });
         if (rc == TTM_OK && mode == 3)
             rc = launch("ttm_compact", st, [&] {
-                hipLaunchKernelGGL(k_compact_rows<float>, dim3(row_blocks), dim3(256),
+                hipLaunchKernelGGL(full_tiles ? k_compact_rows_full<float> : k_compact_rows<float>, dim3(row_blocks), dim3(256),
                                    4 * RowsCfg<float>::WAVE_ELEMS * sizeof(float), st, a,
                                    static_cast<const float *>(X), static_cast<float *>(Y),
                                    static_cast<const float *>(ws));

@@ -28,7 +28,9 @@ SHAPES = [((6, 7, 8), (3, 5, 4)), ((37, 70, 65), (20, 9, 33)), ((1, 1, 1), (1, 1
           # the streaming kernels for W, dX and dC (ragged row counts, a
           # partial last group of 256 columns, J3 below 16)
           ((5, 70, 128), (6, 9, 32)), ((3, 33, 192), (4, 5, 12)), ((2, 1, 64), (3, 2, 4)),
-          ((300, 7, 320), (2, 3, 20))]
+          ((300, 7, 320), (2, 3, 20)),
+          # ... and J2 <= 32 with I2 a multiple of 64: V and R on streaming kernels too
+          ((5, 64, 128), (6, 9, 32)), ((3, 192, 64), (4, 32, 12))]
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: f"I{s[0]}J{s[1]}")

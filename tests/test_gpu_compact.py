@@ -33,7 +33,7 @@ def check(X, mode, h, dt):
     assert err <= TOL[dt], err
 
 
-SHAPES = [(5, 7, 9), (3, 33, 64), (70, 4, 5), (17, 100, 3), (64, 64, 64), (9, 300, 130)]
+SHAPES = [(5, 7, 9), (3, 33, 64), (70, 4, 5), (17, 100, 3), (64, 64, 64), (9, 300, 130), (2, 50, 16), (2, 50, 32)]
 
 
 @pytest.mark.parametrize("dt", [torch.float64, torch.float32], ids=["f64", "f32"])
