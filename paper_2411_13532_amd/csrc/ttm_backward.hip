@@ -16,6 +16,7 @@
 // I1*J3) are split over workgroups and summed in a fixed order.
 #include <algorithm>
 #include <cstring>
+#include <type_traits>
 
 #include "ttm_gemm.hpp"
 #include "ttm_host.hpp"
@@ -73,13 +74,15 @@ void make_bwd_plan(const ttm_shape &s, int math, bool dX, bool dA, bool dB, bool
     const int64_t KT = math == TTM_MATH_F64 ? KT_F64 : KT_F32;
     // partial buffers of the split contractions
     p.part_elems = 0;
+    // partials of a split, then (more than SUM_GROUP of them) their group sums
+    auto split_elems = [](int ks, int64_t mn) { return (int64_t(ks) + (ks > SUM_GROUP ? ceil_div(ks, SUM_GROUP) : 0)) * mn; };
     if (dA) {
         SplitK k = choose_split(p.J1, p.I1, p.NN, 1, KT);
-        if (k.ks > 1) p.part_elems = std::max(p.part_elems, int64_t(k.ks) * p.J1 * p.I1);
+        if (k.ks > 1) p.part_elems = std::max(p.part_elems, split_elems(k.ks, p.J1 * p.I1));
     }
     if (dB) {
         SplitK k = choose_split(p.J2, p.I2, p.I1 * p.J3, 1, KT);
-        if (k.ks > 1) p.part_elems = std::max(p.part_elems, int64_t(k.ks) * p.J2 * p.I2);
+        if (k.ks > 1) p.part_elems = std::max(p.part_elems, split_elems(k.ks, p.J2 * p.I2));
     }
     const int64_t M = p.I1 * p.I2;
     p.skinny = math == TTM_MATH_F32 && p.J3 <= 32 && p.J3 % 4 == 0 && p.I3 % 64 == 0 && M < (int64_t(1) << 31) &&
@@ -87,7 +90,7 @@ void make_bwd_plan(const ttm_shape &s, int math, bool dX, bool dA, bool dB, bool
     p.skinny_vr = p.skinny && p.J2 <= 32 && p.I2 % 64 == 0 && p.I2 < (int64_t(1) << 24) && p.I1 < (int64_t(1) << 31);
     if (dC) {
         SplitK k = choose_split(p.J3, p.I3, p.I1 * p.I2, 1, KT);
-        if (k.ks > 1) p.part_elems = std::max(p.part_elems, int64_t(k.ks) * p.J3 * p.I3);
+        if (k.ks > 1) p.part_elems = std::max(p.part_elems, split_elems(k.ks, p.J3 * p.I3));
         if (p.skinny) {
             const int64_t s0 = std::min<int64_t>(512, ceil_div(M, 64));
             p.dc_rows = round_up(ceil_div(M, s0), 4);
@@ -480,6 +483,21 @@ int run_gemm(GemmArgs a, int64_t batch, bool split, void *part, hipStream_t st, 
     if (rc || k.ks == 1) return rc;
     const int64_t n = a.M * a.N;
     dim3 rg(unsigned(std::min<int64_t>(ceil_div(n, 256), 4096)));
+    if constexpr (std::is_same<T, float>::value) {
+        if (k.ks > SUM_GROUP) {   // groups of SUM_GROUP partials, then the group sums, in order
+            const int ng = int(ceil_div(k.ks, SUM_GROUP));
+            T *pg = static_cast<T *>(part) + int64_t(k.ks) * n;
+            rc = launch("ttm_bwd_sum_splits", st, [&] {
+                hipLaunchKernelGGL(k_sum_groups_f32, dim3(unsigned(ceil_div(n, 256)), unsigned(ng)), dim3(256), 0, st,
+                                   static_cast<const float *>(part), n, k.ks, pg);
+            });
+            if (rc) return rc;
+            return launch("ttm_bwd_sum_splits", st, [&] {
+                hipLaunchKernelGGL(k_sum_splits<T>, rg, dim3(256), 0, st, static_cast<const T *>(pg), n, ng, n,
+                                   static_cast<T *>(final_out));
+            });
+        }
+    }
     return launch("ttm_bwd_sum_splits", st, [&] {
         hipLaunchKernelGGL(k_sum_splits<T>, rg, dim3(256), 0, st, static_cast<const T *>(part), a.M * a.N, k.ks, n,
                            static_cast<T *>(final_out));
