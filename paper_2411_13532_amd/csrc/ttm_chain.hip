@@ -1292,10 +1292,12 @@ __global__ void __launch_bounds__(256) k_mode1(const Mode1Args a) {
 
     // loader: thread (column c = tid % 64, word w = tid / 64 + 4*item) covers rows VE*w .. VE*w+VE-1
     const int lc = tid & 63, lw = tid >> 6;
-    acc_t pre[ITEMS][VE];
+    // V chunks in flight in registers: two ahead of the one being computed
+    // (slots ch % 2), one ahead for bf16x3 with two row blocks per wave
+    acc_t pre2[2][ITEMS][VE];
     // all ITEMS*VE loads of one partial are independent and issued together;
     // rows past the range read row kb (valid) and are zeroed
-    auto fetch = [&](int64_t ch) {
+    auto fetch = [&](int64_t ch, acc_t (&pre)[ITEMS][VE]) __attribute__((always_inline)) {
         const int64_t r0 = kb + ch * KT;
 #pragma unroll
         for (int it = 0; it < ITEMS; ++it)
@@ -1313,7 +1315,7 @@ __global__ void __launch_bounds__(256) k_mode1(const Mode1Args a) {
                 }
         }
     };
-    auto store = [&](int buf) {
+    auto store = [&](int buf, const acc_t (&pre)[ITEMS][VE]) __attribute__((always_inline)) {
 #pragma unroll
         for (int it = 0; it < ITEMS; ++it) {
             const int off = buf * CF::BUFB + lc * CF::ROWB + (lw + 4 * it) * 16;
@@ -1362,15 +1364,7 @@ __global__ void __launch_bounds__(256) k_mode1(const Mode1Args a) {
             }
         }
     };
-    if (nch > 0) {
-        fetch(0);
-        store(0);
-        load_a(0);
-    }
-    __syncthreads();
-    for (int64_t ch = 0; ch < nch; ++ch) {
-        if (ch + 1 < nch) fetch(ch + 1);
-        const int buf = int(ch & 1);
+    auto compute = [&](int buf) __attribute__((always_inline)) {
 #pragma unroll
         for (int kg = 0; kg < 2; ++kg) {
             V16 bh[NW], bl[NW];
@@ -1395,11 +1389,49 @@ __global__ void __launch_bounds__(256) k_mode1(const Mode1Args a) {
                 }
             }
         }
+    };
+    // one chunk: prefetch chunk ch + 2 into the slot chunk ch left, compute
+    // chunk ch, then store chunk ch + 1 (slot 1 - S) and load its A fragments
+    auto step = [&](int64_t ch, auto SLOT) __attribute__((always_inline)) {
+        constexpr int S = decltype(SLOT)::value;
+        if (ch + 2 < nch) fetch(ch + 2, pre2[S]);
+        compute(S);
         if (ch + 1 < nch) {
-            store(buf ^ 1);
+            store(1 - S, pre2[1 - S]);
             load_a(ch + 1);
         }
         __syncthreads();
+    };
+    if constexpr (CF::SPLIT && MW == 2) {
+        // bf16x3 with two row blocks per wave: one chunk ahead (two would take
+        // the registers of a third resident wave per SIMD, measured slower)
+        if (nch > 0) {
+            fetch(0, pre2[0]);
+            store(0, pre2[0]);
+            load_a(0);
+        }
+        __syncthreads();
+        for (int64_t ch = 0; ch < nch; ++ch) {
+            if (ch + 1 < nch) fetch(ch + 1, pre2[0]);
+            compute(int(ch & 1));
+            if (ch + 1 < nch) {
+                store(int((ch + 1) & 1), pre2[0]);
+                load_a(ch + 1);
+            }
+            __syncthreads();
+        }
+    } else {
+        if (nch > 0) {
+            fetch(0, pre2[0]);
+            if (nch > 1) fetch(1, pre2[1]);
+            store(0, pre2[0]);
+            load_a(0);
+        }
+        __syncthreads();
+        for (int64_t ch = 0; ch < nch; ch += 2) {
+            step(ch, std::integral_constant<int, 0>{});
+            if (ch + 1 < nch) step(ch + 1, std::integral_constant<int, 1>{});
+        }
     }
 
     acc_t *Y = static_cast<acc_t *>(a.Y);
