@@ -80,16 +80,10 @@ constexpr int BATCH_PF = 40;
 // 1/32 away from the next integer, far more than its rounding error.
 __device__ __forceinline__ int row_of(int e, float inv_len) { return int((float(e) + 0.5f) * inv_len); }
 
-// n (<= 256) elements of a factor (rows of len) into LDS rows of stride P,
-// loads first (clamped, branch-free), then stores.
+// n (<= 256) elements of a factor (rows of len), already loaded as
+// r[u] = element u * 64 + lane, into LDS rows of stride P.
 template <typename T>
-__device__ __forceinline__ void factor_to_lds(const T *src, int n, int len, int P, T *dst, int lane) {
-    T r[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int e = u * 64 + lane;
-        r[u] = src[e < n ? e : n - 1];
-    }
+__device__ __forceinline__ void factor_regs_to_lds(const T (&r)[4], int n, int len, int P, T *dst, int lane) {
     const float inv = 1.0f / float(len);
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -119,8 +113,11 @@ __global__ void __launch_bounds__(256) k_batched(const BatchArgs a, const T *__r
     constexpr bool MF = std::is_same<T, float>::value;
     const int r16 = lane & 15, g = lane >> 4;
 
-    T pre[BATCH_PF];
-    auto prefetch = [&](const CuboidDesc &d) {
+    // the next cuboid's X (BATCH_PF elements per lane) and three factors (at
+    // most 256 elements each, 4 per lane) are loaded into registers while the
+    // wave works on the current one
+    T pre[BATCH_PF], pf[3][4];
+    auto prefetch = [&](const CuboidDesc &d) __attribute__((always_inline)) {
         const int nx = d.d[0] * d.d[1] * d.d[2];
         const T *xs = X + d.ox;
 #pragma unroll
@@ -128,6 +125,16 @@ __global__ void __launch_bounds__(256) k_batched(const BatchArgs a, const T *__r
             if (u * 64 < nx) {   // uniform: only the rows of 64 that X fills
                 const int e = u * 64 + lane;
                 pre[u] = xs[e < nx ? e : nx - 1];
+            }
+        }
+        const T *fs[3] = {Ag + d.oa, Bg + d.ob, Cg + d.oc};
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            const int n = d.d[3 + f] * d.d[f];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = u * 64 + lane;
+                pf[f][u] = fs[f][e < n ? e : n - 1];
             }
         }
     };
@@ -150,9 +157,9 @@ __global__ void __launch_bounds__(256) k_batched(const BatchArgs a, const T *__r
             for (int e = lane; e < nfac; e += 64) fac[e] = T(0);
             wave_sync();
         }
-        factor_to_lds(Ag + d.oa, J1 * I1, I1, P1, As, lane);
-        factor_to_lds(Bg + d.ob, J2 * I2, I2, P2, Bs, lane);
-        factor_to_lds(Cg + d.oc, J3 * I3, I3, P3, Cs, lane);
+        factor_regs_to_lds(pf[0], J1 * I1, I1, P1, As, lane);
+        factor_regs_to_lds(pf[1], J2 * I2, I2, P2, Bs, lane);
+        factor_regs_to_lds(pf[2], J3 * I3, I3, P3, Cs, lane);
         const float inv3 = 1.0f / float(I3);
 #pragma unroll
         for (int u = 0; u < BATCH_PF; ++u) {
