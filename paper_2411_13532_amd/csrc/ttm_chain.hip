@@ -758,64 +758,13 @@ __global__ void __launch_bounds__(WS_THREADS, 2) k_slab_ws(const SlabArgs a) {
             }
 }
 
-// Mode-2 step for the bf16 forms with the factor loads issued in groups: W is
-// first converted to its bf16 operand pairs (freeing the accumulators), then
-// for each 32-row group the fragments of B (hi and lo) for JG j2 blocks are
-// loaded together before the matrix-core work that uses them, so a tile end
-// waits for (MB / 2) * (JB / JG) rounds of L2 latency instead of one per
-// load.  Same products and order of accumulation as slab_mode2.
-template <int MATH, int MB, int NBW, int JB, int JG>
-__device__ __forceinline__ void slab_mode2_grouped(typename MathTraits<MATH>::accv_t (&vacc)[JB][NBW],
-                                                   typename MathTraits<MATH>::accv_t (&wacc)[MB][NBW],
-                                                   const SlabArgs &a, int jbase, int64_t wrow0, int l16, int g) {
-    static_assert(MATH == M_BF16 || MATH == M_BF16X3, "bf16 forms");
-    constexpr bool X3 = MATH == M_BF16X3;
-    const uint16_t *Bh = static_cast<const uint16_t *>(a.Bhi);
-    const uint16_t *Bl = static_cast<const uint16_t *>(a.Blo);
-    u32x4 wh[MB / 2][NBW], wl[MB / 2][NBW];
-#pragma unroll
-    for (int p = 0; p < MB / 2; ++p)
-#pragma unroll
-        for (int nb = 0; nb < NBW; ++nb) {
-            const float v[8] = {wacc[2 * p][nb][0], wacc[2 * p][nb][1], wacc[2 * p][nb][2], wacc[2 * p][nb][3],
-                                wacc[2 * p + 1][nb][0], wacc[2 * p + 1][nb][1], wacc[2 * p + 1][nb][2],
-                                wacc[2 * p + 1][nb][3]};
-            if constexpr (X3) bf16_split8(v, wh[p][nb], &wl[p][nb]);
-            else wh[p][nb] = bf16_round8(v);
-        }
-#pragma unroll
-    for (int p = 0; p < MB / 2; ++p) {
-#pragma unroll
-        for (int j0 = 0; j0 < JB; j0 += JG) {
-            u32x4 bh[JG], bl[JG];
-#pragma unroll
-            for (int jj = 0; jj < JG; ++jj) {
-                const int64_t off = int64_t((jbase + j0 + jj) * 16 + l16) * a.ldb + wrow0 + 32 * p + 8 * g;
-                bh[jj] = ld16(Bh + off).u;
-                if constexpr (X3) bl[jj] = ld16(Bl + off).u;
-            }
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int jj = 0; jj < JG; ++jj)
-#pragma unroll
-                for (int nb = 0; nb < NBW; ++nb) {
-                    auto &acc = vacc[j0 + jj][nb];
-                    acc = mfma_bf16(bh[jj], wh[p][nb], acc);
-                    if constexpr (X3) {
-                        acc = mfma_bf16(bh[jj], wl[p][nb], acc);
-                        acc = mfma_bf16(bl[jj], wh[p][nb], acc);
-                    }
-                }
-            __builtin_amdgcn_sched_barrier(0);
-        }
-    }
-}
 
-// The same step with the B loads software-pipelined: the tile's B fragments
-// are taken in rounds of four 16-row blocks of j2 (hi and lo) over 32 rows,
-// and the loads of round r + 1 are issued before the products of round r, so
-// each round waits for loads that have had a round of products to land
-// instead of a full L2 round trip.
+// Mode-2 step for the bf16 forms with the B loads software-pipelined: W is
+// first converted to its bf16 operand pairs (freeing the accumulators), then
+// the tile's B fragments are taken in rounds of four 16-row blocks of j2 (hi
+// and lo) over 32 rows, and the loads of round r + 1 are issued before the
+// products of round r, so each round waits for loads that have had a round of
+// products to land instead of a full L2 round trip.
 template <int MATH, int MB, int NBW, int JB>
 __device__ __forceinline__ void slab_mode2_pipe(typename MathTraits<MATH>::accv_t (&vacc)[JB][NBW],
                                                 typename MathTraits<MATH>::accv_t (&wacc)[MB][NBW],
@@ -946,13 +895,6 @@ __device__ __forceinline__ void static_for_seq(F &&f, std::integer_sequence<int,
 template <int N, typename F>
 __device__ __forceinline__ void static_for(F &&f) {
     static_for_seq(f, std::make_integer_sequence<int, N>{});
-}
-// wait for every LDS read in flight; the fragments become available only after it
-template <int N>
-__device__ __forceinline__ void lds_wait_all(V16 (&r)[N]) {
-    asm volatile("s_waitcnt lgkmcnt(0)");
-#pragma unroll
-    for (int i = 0; i < N; ++i) asm volatile("" : "+v"(r[i].u));
 }
 
 template <int MATH, int NBW, int JB>
@@ -1455,15 +1397,17 @@ __global__ void __launch_bounds__(256) k_mode1(const Mode1Args a) {
 }
 
 // Y[j1][j2][j3] = sum_ks Ypart[ks][j1][j2 * J3pad + j3] in increasing ks order.
+// Workgroup r owns the row (j1, j2) = (r / J2, r % J2) (one scalar division
+// per workgroup instead of three per element), its lanes the j3.
 template <typename T>
-__global__ void __launch_bounds__(256) k_mode1_reduce(const Mode1Args a) {
-    const int64_t total = a.J1 * a.J2 * a.J3;
-    const T *Yp = static_cast<const T *>(a.Ypart);
-    T *Y = static_cast<T *>(a.Y);
+__global__ void __launch_bounds__(64) k_mode1_reduce(const Mode1Args a) {
+    const int64_t row = blockIdx.x;
+    const int64_t j1 = row / a.J2, j2 = row - j1 * a.J2;
+    const T *Yp = static_cast<const T *>(a.Ypart) + j1 * a.NN + j2 * a.J3pad;
+    T *Y = static_cast<T *>(a.Y) + row * a.J3;
     const int64_t ps = a.J1pad * a.NN;
-    for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < total; e += int64_t(gridDim.x) * 256) {
-        const int64_t j3 = e % a.J3, j2 = (e / a.J3) % a.J2, j1 = e / (a.J2 * a.J3);
-        const T *p = Yp + j1 * a.NN + j2 * a.J3pad + j3;
+    for (int64_t j3 = threadIdx.x; j3 < a.J3; j3 += 64) {
+        const T *p = Yp + j3;
         T s = T(0);
         int k = 0;
         for (; k + 4 <= a.KS; k += 4) {   // four loads in flight, summed in order
@@ -1471,7 +1415,7 @@ __global__ void __launch_bounds__(256) k_mode1_reduce(const Mode1Args a) {
             s += v0; s += v1; s += v2; s += v3;
         }
         for (; k < a.KS; ++k) s += p[k * ps];
-        Y[e] = s;
+        Y[j3] = s;
     }
 }
 
@@ -1586,7 +1530,7 @@ static bool make_plan(const ttm_shape &s, int xdt, int math, ChainPlan &p) {
     p.total = off;
     // launch-grid limits
     if (I1 * p.S > 0x7fffffffLL || p.n_j3_tiles > 65535 || p.n_j2_tiles > 65535 || p.n_m1_tiles > 65535 ||
-        p.J2pad * p.J3pad / 64 > 0x7fffffffLL || p.KS > 65535)
+        p.J2pad * p.J3pad / 64 > 0x7fffffffLL || p.KS > 65535 || J1 * J2 > 0x7fffffffLL)
         return false;
     return true;
 }
@@ -1711,9 +1655,9 @@ static int dispatch_mode1(const ChainPlan &p, const Mode1Args &a, hipStream_t st
     if (p.m1_NW == 1) rc = p.m1_MW == 1 ? go(k_mode1<MATH, 1, 1>) : go(k_mode1<MATH, 2, 1>);
     else rc = p.m1_MW == 1 ? go(k_mode1<MATH, 1, 4>) : go(k_mode1<MATH, 2, 4>);
     if (rc || p.KS == 1) return rc;
-    const int64_t total = a.J1 * a.J2 * a.J3;
-    dim3 rgrid(unsigned(std::min<int64_t>(ceil_div(total, 256), 8192)));
-    return launch("ttm_mode1_reduce", st, [&] { hipLaunchKernelGGL((k_mode1_reduce<acc_t>), rgrid, dim3(256), 0, st, a); });
+    return launch("ttm_mode1_reduce", st, [&] {
+        hipLaunchKernelGGL((k_mode1_reduce<acc_t>), dim3(unsigned(a.J1 * a.J2)), dim3(64), 0, st, a);
+    });
 }
 
 template <int MATH>
