@@ -1503,11 +1503,13 @@ static bool make_plan(const ttm_shape &s, int xdt, int math, ChainPlan &p) {
     p.lda = round_up(I1, KC);
 
     // mode-1 kernel: split the i1 range while the column tiles alone leave the
-    // GPU short of workgroups, keeping the partials at most half of V's size
+    // GPU short of workgroups (about 512 in all: measured at 1024^3 -> 128^3,
+    // fewer, longer splits beat about 1024 once V is prefetched ahead),
+    // keeping the partials at most half of V's size
     {
         const int64_t NN = p.J2pad * p.J3pad;
         const int64_t wg = (NN / 64) * p.n_m1_tiles;
-        int64_t ks = ceil_div(1024, wg);
+        int64_t ks = ceil_div(512, wg);
         const int64_t ks_bytes = (I1 * p.P) / (2 * p.J1pad);
         if (ks > ks_bytes) ks = ks_bytes;
         if (ks > ceil_div(I1, KC)) ks = ceil_div(I1, KC);
