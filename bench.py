@@ -13,7 +13,9 @@ A step is one full chain (factor preparation, the fused mode-3/mode-2 slab
 kernel, the mode-1 kernel) on inputs already resident in HBM.  `value` is the
 useful GFLOP/s, 2 (J I^3 + J^2 I^2 + J^3 I) per chain; split-precision extra
 products are not counted.  `roofline` is for the dominant kernel (the slab
-kernel), timed with HIP events recorded by the library on the launch stream.
+kernel), timed with HIP events recorded by the library on the launch stream
+in a second pass after the timed steps.  Step times are medians over the
+timed steps (one HIP event after each step on the stream).
 
 Other workloads: --workload c2 (X 512^3 float32, J = 64, float32),
 c4 (20000 ragged cuboids), c5 (X 256^3 float32, J = 32, forward + adjoint),
@@ -70,32 +72,49 @@ def measured_traffic(tag, per_launch_units=1.0):
     return float(t["bytes_per_launch"]) * per_launch_units
 
 
-def timed(fn, steps, warmup, torch, ttm=None):
-    """Average ms per call over `steps` calls after `warmup` untimed ones.
-    With `ttm`, the library's per-launch HIP events (recorded on each kernel's
-    own stream) time every kernel over the same timed region; returns
-    (ms, wall seconds, {kernel: average ms per call of fn})."""
+def timed(fn, steps, warmup, torch):
+    """`warmup` untimed calls, then `steps` timed ones with a HIP event on the
+    current stream after each call (no synchronisation inside the loop).
+    Returns the median, mean and minimum ms per call and the wall seconds."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
-    if ttm is not None:
-        ttm.timing_enable(True)
-        ttm.timing_collect()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = time.perf_counter()
-    e0.record()
-    for _ in range(steps):
+    ev[0].record()
+    for k in range(steps):
         fn()
-    e1.record()
+        ev[k + 1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kt = None
-    if ttm is not None:
-        t = ttm.timing_collect()
-        ttm.timing_enable(False)
-        kt = {k: v[1] / steps for k, v in t.items()}
-    return e0.elapsed_time(e1) / steps, wall, kt
+    per = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)])
+    return {"median": float(np.median(per)), "mean": float(per.mean()), "min": float(per.min()), "wall": wall}
+
+
+def kernel_times(fn, steps, torch, ttm):
+    """Second pass, separate from the timed steps: the library's per-launch
+    HIP events (recorded on each kernel's own launch stream) over `steps`
+    calls.  Returns {kernel: (launches per call, average ms per launch)}."""
+    torch.cuda.synchronize()
+    ttm.timing_enable(True)
+    ttm.timing_collect()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    t = ttm.timing_collect()
+    ttm.timing_enable(False)
+    return {k: (v[0] / steps, v[1] / v[0]) for k, v in t.items()}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def rel_err(y, ref):
@@ -112,23 +131,23 @@ def bench_dense_precision(args, torch, ttm):
     X = p["X"].to(dev)
     fs = [torch.from_numpy(p[k]).to(dev) for k in "ABC"]
     flops = chain_flops(I, J)
-    out = {}
     forms = {}
     Ys = {}
-    plan = [("bf16x3", args.steps), ("f32", max(3, args.steps // 4)), ("bf16", args.steps)]
-    plan = [f for f in plan if f[0] in args.forms.split(",")]
-    for math, steps in plan:
+    kt = {}
+    plan = [f for f in ("bf16x3", "f32", "bf16") if f in args.forms.split(",")]
+    for math in plan:
         wsm = torch.empty(ttm.chain_workspace_size((I,) * 3, (J,) * 3, torch.bfloat16, math), dtype=torch.uint8,
                           device=dev)
         Y = torch.empty((J, J, J), dtype=torch.float32, device=dev)
         fn = lambda: ttm.chain(X, *fs, math=math, out=Y, workspace=wsm)
-        ms, wall, kt = timed(fn, steps, args.warmup, torch, ttm)
-        forms[math] = {"ms_per_step": ms, "gflops": flops / (ms * 1e-3) / 1e9, "steps": steps,
-                       "kernel_ms": {k: round(v, 4) for k, v in kt.items()}}
+        t = timed(fn, args.steps, args.warmup, torch)
+        kt[math] = kernel_times(fn, args.steps, torch, ttm)
+        forms[math] = {"ms_per_step": t["median"], "ms_mean": t["mean"], "ms_min": t["min"],
+                       "gflops": flops / (t["median"] * 1e-3) / 1e9, "steps": args.steps,
+                       "kernel_ms": {k: round(v[1], 4) for k, v in kt[math].items()}}
         Ys[math] = Y.clone()
-        print(f"# {math}: {ms:.3f} ms/step, kernels {kt}", file=sys.stderr, flush=True)
-        if math == "bf16x3":
-            out["ms"], out["wall"], out["kernels"] = ms, wall, kt
+        print(f"# {math}: {t['median']:.3f} ms/step (median), kernels {forms[math]['kernel_ms']}",
+              file=sys.stderr, flush=True)
     # the oracle on the whole step (every output, X read as float32 and
     # widened element by element, float64 arithmetic): the CPU baseline and
     # the accuracy of every form
@@ -140,38 +159,42 @@ def bench_dense_precision(args, torch, ttm):
         t0 = time.perf_counter()
         ref = oracle.chain(X_np, A64, B64, C64, order=(3, 2, 1))
         dt = time.perf_counter() - t0
-        cpu = {"value": flops / dt / 1e9, "unit": "GFLOP/s", "cores": oracle.num_threads(), "kind": "oracle",
+        cpu = {"value": round(flops / dt / 1e9, 2), "unit": "GFLOP/s", "cores": oracle.num_threads(),
+               "kind": "oracle", "cpu_model": cpu_model(),
                "sample": f"the whole 1024^3 -> 128^3 step (all of Y, mode-3 product first), "
                          f"{flops / 1e9:.1f} GFLOP in {dt:.1f} s"}
         for math, Y in Ys.items():
             forms[math]["rel_err_vs_oracle"] = rel_err(Y.double().cpu().numpy(), ref)
         del X_np
-    # dominant kernel: the slab kernel (modes 3 and 2); algorithmic bytes are
-    # X (bf16) + the partial V it writes (float) + the factor operands it reads
-    slab_ms = out["kernels"]["ttm_slab"]
-    x_bytes = I ** 3 * 2
-    v_bytes = I * J * J * 4
-    fac_bytes = 2 * (J * I * 4)            # B and C as bf16 hi + lo
-    slab_bytes = x_bytes + v_bytes + fac_bytes
-    slab_mfma = 2 * (2.0 * J * I ** 3) + 3 * (2.0 * J * J * I * I)
-    gbs = slab_bytes / (slab_ms * 1e-3) / 1e9
-    tflops = slab_mfma / (slab_ms * 1e-3) / 1e12
-    t_hbm = slab_bytes / (HBM_PEAK_GBS * 1e9)
-    t_mfma = slab_mfma / (MFMA_BF16_TFLOPS * 1e12)
+    # dominant kernel: the slab kernel (modes 3 and 2).  Algorithmic bytes of
+    # the step: X (bf16) read once, Y (float) written once, the three stored
+    # float factors read once; the slab kernel is the one that moves them
+    # (the V partial it writes and the mode-1 kernel reads is the
+    # implementation's own intermediate and shows up under `traffic`).
+    # MFMA flops issued in bf16x3: two products for mode 3 (X is exact
+    # bf16), three for modes 2 and 1.
+    ms = forms["bf16x3"]["ms_per_step"]
+    slab_ms = kt["bf16x3"]["ttm_slab"][1]
+    alg_bytes = I ** 3 * 2 + J ** 3 * 4 + 3 * J * I * 4
+    mfma = 2 * (2.0 * J * I ** 3) + 3 * (2.0 * J * J * I * I) + 3 * (2.0 * J ** 3 * I)
+    t_hbm = alg_bytes / (HBM_PEAK_GBS * 1e9)
+    t_mfma = mfma / (MFMA_BF16_TFLOPS * 1e12)
+    gbs = alg_bytes / (slab_ms * 1e-3) / 1e9
     if t_hbm >= t_mfma:
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(gbs / HBM_PEAK_GBS, 4)}
     else:
-        roof = {"bound": "mfma", "achieved": round(tflops, 1), "peak": MFMA_BF16_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(tflops / MFMA_BF16_TFLOPS, 4)}
+        tf = mfma / (slab_ms * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": round(tf, 1), "peak": MFMA_BF16_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(tf / MFMA_BF16_TFLOPS, 4)}
     roof["traffic"] = measured_traffic("ttm_slab_c3_bf16x3")
-    roof["kernel"] = "ttm_slab (k_slab_lc<bf16x3, 8 waves, 256-row tiles, X and C through LDS, 128-byte chunks>)"
+    roof["kernel"] = "ttm_slab (k_slab_lc<bf16x3>)"
     roof["kernel_ms"] = round(slab_ms, 4)
-    roof["algorithmic_bytes"] = slab_bytes
-    roof["mfma_flops"] = slab_mfma
-    roof["mfma_frac"] = round(tflops / MFMA_BF16_TFLOPS, 4)
+    roof["algorithmic_bytes"] = alg_bytes
+    roof["mfma_flops"] = mfma
+    roof["mfma_frac"] = round(mfma / (slab_ms * 1e-3) / 1e12 / MFMA_BF16_TFLOPS, 4)
+    roof["step_frac"] = round(max(t_hbm, t_mfma) / (ms * 1e-3), 4)
     roof["copy_ceiling_gbs"] = round(copy_gbs(torch, ttm, 1 << 30, 10), 1)
-    ms = out["ms"]
     speedup = (round(forms["f32"]["ms_per_step"] / forms["bf16x3"]["ms_per_step"], 3)
                if "f32" in forms and "bf16x3" in forms else None)
     line = {
@@ -198,8 +221,8 @@ def copy_gbs(torch, ttm, nbytes, reps):
     """Practical HBM ceiling: read + write bytes per second of the library's copy kernel."""
     src = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
     dst = torch.empty_like(src)
-    ms, _, _ = timed(lambda: ttm.stream_copy(dst, src), reps, 2, torch)
-    return 2 * nbytes / (ms * 1e-3) / 1e9
+    t = timed(lambda: ttm.stream_copy(dst, src), reps, 2, torch)
+    return 2 * nbytes / (t["median"] * 1e-3) / 1e9
 
 
 def bench_copy(args, torch, ttm):
@@ -225,7 +248,8 @@ def bench_c2(args, torch, ttm):
         ws = torch.empty(ttm.chain_workspace_size((I,) * 3, (J,) * 3, torch.float32, math), dtype=torch.uint8, device=dev)
         Y = torch.empty((J, J, J), dtype=torch.float32, device=dev)
         fn = lambda: ttm.chain(X, *fs, math=math, out=Y, workspace=ws)
-        ms, _, kt = timed(fn, args.steps, args.warmup, torch, ttm)
+        ms = timed(fn, args.steps, args.warmup, torch)["median"]
+        kt = {k: round(v[1], 4) for k, v in kernel_times(fn, args.steps, torch, ttm).items()}
         res[math] = {"ms_per_step": ms, "gflops": chain_flops(I, J) / (ms * 1e-3) / 1e9, "kernel_ms": kt}
     ms = res["f32"]["ms_per_step"]
     slab = res["f32"]["kernel_ms"]["ttm_slab"]
@@ -260,7 +284,7 @@ def bench_c4(args, torch, ttm):
     res = {}
     for mode in ("persistent", "graph"):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        tot = 0.0
+        per = []
         for _ in range(args.warmup):
             cold(mode)
         for _ in range(args.steps):
@@ -269,9 +293,9 @@ def bench_c4(args, torch, ttm):
             plan.run(*bufs, Y=Y, mode=mode)
             e1.record()
             torch.cuda.synchronize()
-            tot += e0.elapsed_time(e1)
-        res[mode] = tot / args.steps
-    ms_loop, _, _ = timed(lambda: plan.run(*bufs, Y=Y, mode="loop"), 2, 1, torch)
+            per.append(e0.elapsed_time(e1))
+        res[mode] = float(np.median(per))
+    ms_loop = timed(lambda: plan.run(*bufs, Y=Y, mode="loop"), 2, 1, torch)["median"]
     ms = res["graph"]
     gbs = nbytes / (ms * 1e-3) / 1e9
     return {"metric": "batched TTM-chain GFLOP/s + % roofline", "value": round(flops / (ms * 1e-3) / 1e9, 1),
@@ -293,13 +317,13 @@ def bench_c5(args, torch, ttm):
     X, A, B, C, T = (torch.from_numpy(p[k]).to(dev) for k in "XABCT")
     Y = torch.empty((J, J, J), dtype=torch.float32, device=dev)
     fwd = lambda: ttm.chain(X, A, B, C, math="f32", out=Y)
-    ms_f, _, _ = timed(fwd, args.steps, args.warmup, torch)
+    ms_f = timed(fwd, args.steps, args.warmup, torch)["median"]
     G = Y - T
     bwd = lambda: ttm.chain_backward(G, X, A, B, C, math="f32")
     # the step time without per-kernel events (fourteen short launches: the
     # events' host cost would show in it), then the kernel breakdown
-    ms_b, _, _ = timed(bwd, args.steps, args.warmup, torch)
-    _, _, kt_b = timed(bwd, args.steps, 1, torch, ttm)
+    ms_b = timed(bwd, args.steps, args.warmup, torch)["median"]
+    kt_b = {k: n * v for k, (n, v) in kernel_times(bwd, args.steps, torch, ttm).items()}
     fl_f = chain_flops(I, J)
     return {"metric": "TTM-chain forward+adjoint GFLOP/s", "value": round(fl_f / ((ms_f) * 1e-3) / 1e9, 1),
             "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -328,8 +352,8 @@ def bench_c6(args, torch, ttm):
         # preprocessing step), outside the timed sweeps
         ttm.compact_apply(X, mode, out=Y, workspace=ws)
         fn = lambda: ttm.compact_apply(X, mode, out=Y, workspace=ws, prepared=True)
-        ms, _, kt = timed(fn, args.steps, args.warmup, torch, ttm)
-        kms = kt["ttm_compact"]
+        ms = timed(fn, args.steps, args.warmup, torch)["median"]
+        kms = kernel_times(fn, args.steps, torch, ttm)["ttm_compact"][1]
         per_mode[mode] = {"ms": round(ms, 4), "kernel_ms": round(kms, 4),
                           "gbs": round(nbytes / (kms * 1e-3) / 1e9, 1)}
     ms = sum(v["ms"] for v in per_mode.values())

@@ -63,8 +63,14 @@ typedef enum { TTM_F64 = 0, TTM_F32 = 1, TTM_BF16 = 2 } ttm_dtype;
  *  BF16X3 : every float operand v is split into hi = rne_bf16(v) and
  *           lo = rne_bf16(v - hi); a product is formed as hi*hi' + hi*lo' +
  *           lo*hi' on bfloat16 matrix cores with float accumulation, and
- *           intermediates stay float and are split again.  Reaches float-level
- *           accuracy at bfloat16 matrix-core rates.
+ *           intermediates stay float and are split again.  The split
+ *           keeps about 16 significant bits of every operand, so the error
+ *           is about 2^-17 times the sum of the magnitudes of the terms of an
+ *           output: near float's on well-conditioned data (relative error
+ *           about 7e-6 on the 1024^3 -> 128^3 Gaussian workload), but up to
+ *           about 2^-17 times the condition number where terms cancel (about
+ *           4e-5 for the compact-scheme derivative factors of Sec. 4.2,
+ *           whose sums cancel heavily).  Runs at bfloat16 matrix-core rates.
  */
 typedef enum { TTM_MATH_F64 = 0, TTM_MATH_F32 = 1, TTM_MATH_BF16 = 2, TTM_MATH_BF16X3 = 3 } ttm_math;
 
@@ -80,25 +86,21 @@ const char *ttm_status_string(int status);
 int ttm_version(void);
 
 /*
- * Slab-kernel selection (process-wide), for tests and measurements that
- * compare the implementations of the fused mode-3/mode-2 step:
+ * Slab-kernel selection (process-wide), a measurement and test hook that
+ * compares the implementations of the fused mode-3/mode-2 step; results of
+ * every selection agree with the operator above.  Changing it while another
+ * thread runs ttm_chain only changes which kernel that call launches.
  *   0 (default): with bf16 X, the bf16 or bf16x3 form and four column
  *      waves (J3 above 32), where rows are 16-byte aligned, I3 a multiple
  *      of 64 and the i2 range of a workgroup at least 256 rows (the grid
  *      splits I2 into ranges of a multiple of 128 rows so as to reach about
- *      1024 workgroups), the kernel of 5; otherwise, where X is already in the
+ *      1024 workgroups), the kernel of 3; otherwise, where X is already in the
  *      operand format with 16-byte aligned rows and I3 a multiple of 256
  *      bytes, the kernel of 2; the register-staged kernel elsewhere;
  *   1: the register-staged kernel everywhere;
  *   2: direct-to-LDS, 256-byte chunks, two stages, with the fragments of C
  *      loaded from L2 by every wave (where it applies, else as 1);
- *   3: direct-to-LDS, 512-byte chunks, two stages, one workgroup per
- *      compute unit (where I3 is a multiple of 512 bytes, else as 2);
- *   4: direct-to-LDS with a dedicated copy wave (three stages, two chunks in
- *      flight), which also widens or rounds X of another storage type while
- *      reading it (where rows are aligned and I3 a multiple of 256 bytes,
- *      else as 1);
- *   5: direct-to-LDS for both X and C, eight waves over 256-row tiles,
+ *   3: direct-to-LDS for both X and C, eight waves over 256-row tiles,
  *      128-byte chunks, three X stages and two C stages (where the
  *      conditions of 0 hold, else as 1).
  * Returns TTM_ERR_INVALID_ARG for any other value.

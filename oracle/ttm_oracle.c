@@ -288,27 +288,51 @@ int ttmo_batched(int64_t count, const int64_t *dims, const double *X, const doub
 }
 
 /* ---------------------------------------------------------------------------
- * Thomas algorithm for one tridiagonal system (Sec. 2.1, Alg. "Thomas"):
- * a = lower band (a[0] unused), b = diagonal, c = upper band (c[n-1] unused),
- * d = right-hand side, u = solution.  Forward elimination then back
- * substitution; the modified upper band is kept in a scratch copy so the
- * caller's c is not overwritten.
+ * One tridiagonal system T u = d (Sec. 2.1: the Thomas algorithm is Gaussian
+ * elimination without pivoting specialised to the band).  a = lower band
+ * (a[0] unused), b = diagonal, c = upper band (c[n-1] unused).
+ *
+ * Written here as an explicit factorisation T = L U and two substitutions:
+ *   L is unit lower bidiagonal with sub-diagonal m[i] (row i, column i-1),
+ *   U is upper bidiagonal with diagonal p[i] and the unchanged super-diagonal
+ *   c, so row i of L U gives a[i] = m[i] p[i-1] and b[i] = m[i] c[i-1] + p[i].
+ * Then L y = d (forward) and U u = y (backward).
  * ------------------------------------------------------------------------- */
+static void tri_lu(int64_t n, const double *a, const double *b, const double *c, double *m, double *p)
+{
+    p[0] = b[0];
+    m[0] = 0.0;
+    for (int64_t i = 1; i < n; ++i) {
+        m[i] = a[i] / p[i - 1];
+        p[i] = b[i] - m[i] * c[i - 1];
+    }
+}
+
+/* L y = d with L = I + (sub-diagonal m) */
+static void tri_forward(int64_t n, const double *m, const double *d, double *y)
+{
+    y[0] = d[0];
+    for (int64_t i = 1; i < n; ++i) y[i] = d[i] - m[i] * y[i - 1];
+}
+
+/* U u = y with U = diag(p) + (super-diagonal c) */
+static void tri_backward(int64_t n, const double *p, const double *c, const double *y, double *u)
+{
+    u[n - 1] = y[n - 1] / p[n - 1];
+    for (int64_t i = n - 2; i >= 0; --i) u[i] = (y[i] - c[i] * u[i + 1]) / p[i];
+}
+
 int ttmo_thomas(int64_t n, const double *a, const double *b, const double *c,
                 const double *d, double *u)
 {
     if (n < 1) return -1;
-    double *cp = (double *)malloc(sizeof(double) * (size_t)n);
-    u[0] = d[0] / b[0];
-    cp[0] = c[0] / b[0];
-    for (int64_t i = 1; i < n; ++i) {
-        const double w = 1.0 / (b[i] - a[i] * cp[i - 1]);
-        u[i] = w * (d[i] - a[i] * u[i - 1]);
-        cp[i] = w * c[i];
-    }
-    for (int64_t i = n - 2; i >= 0; --i)
-        u[i] -= cp[i] * u[i + 1];
-    free(cp);
+    double *m = (double *)malloc(sizeof(double) * (size_t)n);
+    double *p = (double *)malloc(sizeof(double) * (size_t)n);
+    double *y = (double *)malloc(sizeof(double) * (size_t)n);
+    tri_lu(n, a, b, c, m, p);
+    tri_forward(n, m, d, y);
+    tri_backward(n, p, c, y, u);
+    free(m); free(p); free(y);
     return 0;
 }
 

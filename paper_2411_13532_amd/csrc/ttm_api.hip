@@ -59,15 +59,15 @@ std::atomic<int> g_slab_mode{0};
 int slab_kernel_mode() { return g_slab_mode.load(std::memory_order_relaxed); }
 
 int device_cu_count() {
-    static int cached[64] = {0};
+    static std::atomic<int> cached[64];
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-    if (!cached[dev]) {
-        int n = 0;
+    int n = cached[dev].load(std::memory_order_relaxed);
+    if (!n) {
         if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
-        cached[dev] = n;
+        cached[dev].store(n, std::memory_order_relaxed);
     }
-    return cached[dev];
+    return n;
 }
 
 }  // namespace ttm
@@ -89,7 +89,7 @@ const char *ttm_status_string(int status) {
 int ttm_version(void) { return 1 * 10000 + 0 * 100 + 0; }
 
 int ttm_set_slab_kernel(int mode) {
-    if (mode < 0 || mode > 5) return TTM_ERR_INVALID_ARG;
+    if (mode < 0 || mode > 3) return TTM_ERR_INVALID_ARG;
     ttm::g_slab_mode.store(mode, std::memory_order_relaxed);
     return TTM_OK;
 }

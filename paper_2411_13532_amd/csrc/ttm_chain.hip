@@ -15,6 +15,7 @@
 //   3. k_mode1 : Y = A V_(1), summing the partials of V in a fixed order
 //      (no atomics, so every call is bitwise reproducible).
 #include <algorithm>
+#include <atomic>
 #include <type_traits>
 #include <utility>
 
@@ -400,15 +401,13 @@ __global__ void __launch_bounds__(SLAB_THREADS, 2) k_slab(const SlabArgs a) {
 // exactly the chunk about to be used.  Inside a chunk the 16-byte words of a
 // row are XOR-swizzled by (row & 15): a 16-byte LDS read is served 16 lanes
 // at a time over 64 banks (256 bytes), and the 16 rows of an operand
-// fragment then land on 16 distinct 16-byte bank groups.  Chunks are 256 bytes per row
-// (64 KiB of LDS, two workgroups per compute unit) or 512 bytes per row
-// (128 KiB, one workgroup per compute unit with the whole register file, and
-// twice the matrix-core work per chunk to cover the HBM latency).  Rows past the end of a slab
-// range are read from a clamped (valid) row and their W rows zeroed before
-// the mode-2 step.
+// fragment then land on 16 distinct 16-byte bank groups.  Chunks are 256
+// bytes per row (64 KiB of LDS, two workgroups per compute unit).  Rows past
+// the end of a slab range are read from a clamped (valid) row and their W
+// rows zeroed before the mode-2 step.
 // ---------------------------------------------------------------------------
-template <int MATH, int WC, int NBW, int JB, int ROWB>
-__global__ void __launch_bounds__(SLAB_THREADS, ROWB == 512 ? 1 : 2) k_slab_dma(const SlabArgs a) {
+template <int MATH, int WC, int NBW, int JB>
+__global__ void __launch_bounds__(SLAB_THREADS, 2) k_slab_dma(const SlabArgs a) {
     typedef MathTraits<MATH> TR;
     typedef typename TR::lds_t LT;
     typedef typename TR::accv_t accv_t;
@@ -416,6 +415,7 @@ __global__ void __launch_bounds__(SLAB_THREADS, ROWB == 512 ? 1 : 2) k_slab_dma(
     typedef typename TR::fac_t FT;
     constexpr int WR = 4 / WC, RW = SLAB_TM / WR, MB = RW / 16;
     constexpr int VE = TR::VE, KG = TR::KG;
+    constexpr int ROWB = 256;                           // bytes of a row per chunk
     constexpr int KC = ROWB / int(sizeof(LT));         // k per chunk
     constexpr int NKG = ROWB / 64;                      // k-groups per chunk
     constexpr int STAGE = SLAB_TM * ROWB;
@@ -559,27 +559,6 @@ __global__ void __launch_bounds__(SLAB_THREADS, ROWB == 512 ? 1 : 2) k_slab_dma(
             }
 }
 
-// ---------------------------------------------------------------------------
-// k_slab_ws: the direct-to-LDS slab kernel with a dedicated copy wave.
-//
-// A vector-memory wait on gfx9 is in order: waiting for any load also waits
-// for every older one.  When the compute waves both start the X copy of the
-// next chunk and load their factor fragments, each factor-fragment wait also
-// waits for that copy, which exposes the HBM latency once per chunk.  Here a
-// fifth wave issues all X copies (three LDS stages, two chunks in flight) and
-// waits only for them; the four compute waves issue only the short factor
-// loads.  One barrier per chunk: before it the copy wave waits until chunk q
-// has landed (at most the 32 copies of chunk q+1 still in flight); after it
-// the copy wave starts chunk q+2 into the stage chunk q-1 used, and the
-// compute waves work on chunk q.  Every wave executes the same number of
-// barriers, and the loop bounds are uniform, so the grid always drains.
-// ---------------------------------------------------------------------------
-constexpr int WS_ROWB = 256;
-constexpr int WS_NS = 3;
-constexpr int WS_STAGE = SLAB_TM * WS_ROWB;          // 32 KiB
-constexpr int WS_THREADS = SLAB_THREADS + 64;
-constexpr int WS_NDMA = WS_STAGE / 1024;             // copy instructions per stage (one wave)
-
 // s_waitcnt with only the vector-memory count limited (gfx9 encoding:
 // vmcnt bits [3:0] and [15:14], expcnt and lgkmcnt at their maxima).
 template <int N>
@@ -587,177 +566,6 @@ __device__ __forceinline__ void wait_vmcnt() {
     static_assert(N >= 0 && N < 64, "vmcnt range");
     __builtin_amdgcn_s_waitcnt((N & 0xf) | ((N >> 4) << 14) | (0x7 << 4) | (0xf << 8));
 }
-
-// Operand fragment of X for one k-group from a swizzled stage row (16-byte
-// words w stored at w ^ (row & 15)).  X keeps its storage type in LDS; a
-// bf16 X feeding float products is widened here, a float X feeding bf16
-// products is rounded (and split for bf16x3) here.
-template <int MATH, typename XT>
-__device__ __forceinline__ void ws_afrag(const unsigned char *rowp, int row, int kg, int g, V16 &ah, V16 &al) {
-    constexpr int KG = MathTraits<MATH>::KG;
-    const int sw = row & 15;
-    if constexpr (std::is_same<XT, typename MathTraits<MATH>::lds_t>::value) {
-        ah.u = *reinterpret_cast<const u32x4 *>(rowp + ((kg * 4 + g) ^ sw) * 16);
-    } else if constexpr (MATH == M_F32) {            // bf16 X: 4 values = 8 bytes
-        const int byte = (kg * KG + 4 * g) * 2;
-        const u32x2 h = *reinterpret_cast<const u32x2 *>(rowp + (((byte >> 4) ^ sw) << 4) + (byte & 15));
-        ah.f[0] = __uint_as_float(h[0] << 16);
-        ah.f[1] = __uint_as_float(h[0] & 0xffff0000u);
-        ah.f[2] = __uint_as_float(h[1] << 16);
-        ah.f[3] = __uint_as_float(h[1] & 0xffff0000u);
-    } else {                                          // float X, bf16 products: 8 values = 32 bytes
-        const int w = (kg * KG + 8 * g) * 4 / 16;
-        V16 lo4, hi4;
-        lo4.u = *reinterpret_cast<const u32x4 *>(rowp + ((w ^ sw) << 4));
-        hi4.u = *reinterpret_cast<const u32x4 *>(rowp + (((w + 1) ^ sw) << 4));
-        const float v[8] = {lo4.f[0], lo4.f[1], lo4.f[2], lo4.f[3], hi4.f[0], hi4.f[1], hi4.f[2], hi4.f[3]};
-        if constexpr (MATH == M_BF16X3) bf16_split8(v, ah.u, &al.u);
-        else ah.u = bf16_round8(v);
-    }
-}
-
-template <int MATH, typename XT, int WC, int NBW, int JB>
-__global__ void __launch_bounds__(WS_THREADS, 2) k_slab_ws(const SlabArgs a) {
-    typedef MathTraits<MATH> TR;
-    typedef typename TR::accv_t accv_t;
-    typedef typename TR::acc_t acc_t;
-    typedef typename TR::fac_t FT;
-    constexpr int WR = 4 / WC, RW = SLAB_TM / WR, MB = RW / 16;
-    constexpr int VE = TR::VE, KG = TR::KG;
-    constexpr int XVE = 16 / int(sizeof(XT));        // X values per 16-byte word
-    constexpr int KC = WS_ROWB / int(sizeof(XT));    // k per chunk
-    constexpr int NKG = KC / KG;                     // k-groups per chunk
-    constexpr bool XLO = (MATH == M_BF16X3) && std::is_same<XT, float>::value;
-    static_assert(MB >= 2 && MB % 2 == 0, "row blocks per wave");
-
-    __shared__ __align__(1024) unsigned char stages[WS_NS * WS_STAGE];
-
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t i1 = blockIdx.x / a.S;
-    const int s = int(blockIdx.x % a.S);
-    const int64_t row_begin = int64_t(s) * a.rows_per_split;
-    const int64_t row_end = a.I2 < row_begin + a.rows_per_split ? a.I2 : row_begin + a.rows_per_split;
-    const int64_t nrows = row_end > row_begin ? row_end - row_begin : 0;
-    const int64_t nk = a.I3 / KC;
-    const int64_t ntiles = ceil_div(nrows, SLAB_TM);
-    const int64_t nq = ntiles * nk;
-    const XT *Xs = static_cast<const XT *>(a.X) + i1 * a.I2 * a.I3;
-
-    if (wave == 4) {
-        // ---- copy wave ----
-        const int drow = lane >> 4, dpos = lane & 15;
-        auto dma = [&](int64_t q) {
-            const int64_t t = q / nk, kc = q - t * nk;
-            unsigned char *stage = stages + int(q % WS_NS) * WS_STAGE;
-            const int64_t r0 = row_begin + t * SLAB_TM;
-#pragma unroll 8
-            for (int j = 0; j < WS_NDMA; ++j) {
-                const int row = 4 * j + drow;
-                int64_t grow = r0 + row;
-                grow = grow < row_end ? grow : row_end - 1;
-                const int word = dpos ^ (row & 15);
-                dma16_to_lds(Xs + grow * a.I3 + kc * KC + word * XVE, stage + 4 * j * WS_ROWB);
-            }
-        };
-        if (nq > 0) dma(0);
-        if (nq > 1) dma(1);
-        for (int64_t q = 0; q < nq; ++q) {
-            if (q + 1 < nq) wait_vmcnt<WS_NDMA>();   // chunk q landed; chunk q+1 may be in flight
-            else wait_vmcnt<0>();
-            __builtin_amdgcn_s_barrier();
-            if (q + 2 < nq) dma(q + 2);
-        }
-        return;
-    }
-
-    // ---- compute waves ----
-    const int wr = wave / WC, wc = wave % WC;
-    const int l16 = lane & 15, g = lane >> 4;
-    const int64_t col0 = int64_t(blockIdx.y) * (WC * NBW * 16) + wc * NBW * 16;
-    const int jbase = int(blockIdx.z) * JB;
-    const FT *Ch = static_cast<const FT *>(a.Chi);
-    const FT *Cl = static_cast<const FT *>(a.Clo);
-
-    accv_t vacc[JB][NBW];
-    accv_t wacc[MB][NBW];
-#pragma unroll
-    for (int jb = 0; jb < JB; ++jb)
-#pragma unroll
-        for (int nb = 0; nb < NBW; ++nb) vacc[jb][nb] = zero_accv<accv_t>();
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-        for (int nb = 0; nb < NBW; ++nb) wacc[mb][nb] = zero_accv<accv_t>();
-
-    int64_t t = 0, kc = 0;
-    for (int64_t q = 0; q < nq; ++q) {
-        __builtin_amdgcn_s_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        const unsigned char *stage = stages + int(q % WS_NS) * WS_STAGE;
-        V16 bh[2][NBW], bl[2][NBW];
-        auto load_c = [&](int slot, int kg) {
-            const int64_t k0 = kc * KC + kg * KG + g * VE;
-#pragma unroll
-            for (int nb = 0; nb < NBW; ++nb) {
-                const int64_t off = (col0 + nb * 16 + l16) * a.ldc + k0;
-                bh[slot][nb] = ld16(Ch + off);
-                if constexpr (MATH == M_BF16X3) bl[slot][nb] = ld16(Cl + off);
-            }
-        };
-        load_c(0, 0);
-#pragma unroll
-        for (int kg = 0; kg < NKG; ++kg) {
-            if (kg + 1 < NKG) load_c((kg + 1) & 1, kg + 1);
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb) {
-                const int row = wr * RW + mb * 16 + l16;
-                V16 ah, al;
-                ws_afrag<MATH, XT>(stage + row * WS_ROWB, row, kg, g, ah, al);
-#pragma unroll
-                for (int nb = 0; nb < NBW; ++nb) {
-                    mma_kgroup<MATH == M_BF16X3 ? M_BF16 : MATH>(wacc[mb][nb], ah, bh[kg & 1][nb]);
-                    if constexpr (MATH == M_BF16X3) mma_kgroup<M_BF16>(wacc[mb][nb], ah, bl[kg & 1][nb]);
-                    if constexpr (XLO) mma_kgroup<M_BF16>(wacc[mb][nb], al, bh[kg & 1][nb]);
-                }
-            }
-        }
-        if (kc == nk - 1) {
-            const int64_t wrow0 = row_begin + t * SLAB_TM + wr * RW;
-            if (row_begin + (t + 1) * SLAB_TM > row_end) {
-#pragma unroll
-                for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const bool dead = wrow0 + mb * 16 + TR::acc_row(g, r) >= row_end;
-#pragma unroll
-                        for (int nb = 0; nb < NBW; ++nb)
-                            if (dead) wacc[mb][nb][r] = acc_t(0);
-                    }
-            }
-            slab_mode2<MATH, MB, NBW, JB>(vacc, wacc, a, jbase, wrow0, l16, g);
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-                for (int nb = 0; nb < NBW; ++nb) wacc[mb][nb] = zero_accv<accv_t>();
-            kc = 0;
-            ++t;
-        } else {
-            ++kc;
-        }
-    }
-
-    acc_t *Vp = static_cast<acc_t *>(a.V) + (i1 * a.P + int64_t(s) * WR + wr) * a.J2pad * a.J3pad;
-#pragma unroll
-    for (int jb = 0; jb < JB; ++jb)
-#pragma unroll
-        for (int nb = 0; nb < NBW; ++nb)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t j2 = int64_t(jbase + jb) * 16 + TR::acc_row(g, r);
-                Vp[j2 * a.J3pad + col0 + nb * 16 + l16] = vacc[jb][nb][r];
-            }
-}
-
 
 // Mode-2 step for the bf16 forms with the B loads software-pipelined: W is
 // first converted to its bf16 operand pairs (freeing the accumulators), then
@@ -853,15 +661,17 @@ __device__ __forceinline__ uint32_t lds_offset(const void *p) {
 // the vector-memory operations it waits for: its own waits for ordinary loads
 // (which return in order among themselves) then count only those loads
 // instead of falling back to waiting for everything, and the copies are waited
-// for explicitly.  No other code of the kernel that uses this relies on m0.
+// for explicitly (wait_vmcnt).  The LDS address is bound to m0 through the
+// operand constraint, so the compiler writes m0 itself and knows it is taken;
+// the s_nop separates that write from the copy that reads it.
 __device__ __forceinline__ void dma16_to_lds_m0(const void *g, uint32_t lds_addr) {
-    asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" : : "v"(g), "s"(lds_addr));
+    asm volatile("s_nop 0\n\tglobal_load_lds_dwordx4 %0, off" : : "v"(g), "{m0}"(lds_addr) : "memory");
 }
 template <int OFF>
 __device__ __forceinline__ u32x4 lds_read16_at(uint32_t addr) {
     static_assert(OFF >= 0 && OFF < 65536 && OFF % 16 == 0, "ds_read_b128 immediate offset");
     u32x4 v;
-    asm volatile("ds_read_b128 %0, %1 offset:%2" : "=v"(v) : "v"(addr), "i"(OFF));
+    asm volatile("ds_read_b128 %0, %1 offset:%2" : "=v"(v) : "v"(addr), "i"(OFF) : "memory");
     return v;
 }
 // wait until at most N LDS reads of this wave are in flight
@@ -1542,77 +1352,59 @@ static int launch_slab(const ChainPlan &p, const SlabArgs &a, hipStream_t st) {
     typedef SlabCfg<MATH, XT> CF;
     dim3 grid(unsigned(a.I1 * a.S), unsigned(p.n_j3_tiles), unsigned(p.n_j2_tiles));
     const size_t lds = CF::lds_bytes();
-    static bool attr_set = false;
-    if (!attr_set) {
-        if (hipFuncSetAttribute(reinterpret_cast<const void *>(&k_slab<MATH, XT, WC, NBW, JB>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)) != hipSuccess)
-            return TTM_ERR_HIP;
-        attr_set = true;
-    }
+    static std::atomic<uint64_t> attr_set{0};
+    if (int rc = ensure_lds_limit(reinterpret_cast<const void *>(&k_slab<MATH, XT, WC, NBW, JB>), lds, attr_set))
+        return rc;
     return launch("ttm_slab", st, [&] {
         hipLaunchKernelGGL((k_slab<MATH, XT, WC, NBW, JB>), grid, dim3(SLAB_THREADS), lds, st, a);
     });
 }
 
-template <int MATH, int WC, int NBW, int JB, int ROWB>
-static int launch_slab_dma(const ChainPlan &p, const SlabArgs &a, hipStream_t st) {
-    dim3 grid(unsigned(a.I1 * a.S), unsigned(p.n_j3_tiles), unsigned(p.n_j2_tiles));
-    return launch("ttm_slab", st, [&] {
-        hipLaunchKernelGGL((k_slab_dma<MATH, WC, NBW, JB, ROWB>), grid, dim3(SLAB_THREADS), 0, st, a);
-    });
-}
-
 // Which direct-to-LDS variant applies (0: none): 16-byte aligned rows and
-// whole chunks along i3.  The two-stage kernels (256 or 512-byte chunks) need
-// X already in the operand format; the copy-wave kernel (returned as 1) widens
-// or rounds X while reading its fragments, so it takes any storage type; the
-// kernel with C in LDS (returned as 128) takes bf16 X with the bf16 forms and
-// four column waves.  Automatic selection takes the kernel with C in LDS where
-// it applies and the row range of a workgroup holds at least one whole
-// 256-row tile (measured at 1024^3 -> 128^3 it runs 15% ahead of the
-// two-stage kernel with bf16x3 and 7% with bf16; with 128-row ranges, as at
-// 256^3 -> 64^3, half of each tile is padding), then the two-stage 256-byte kernel
-// where X is in the operand format, and the register-staged kernel otherwise:
-// the copy-wave kernel, which fits one workgroup per CU with its three 32 KiB
-// stages, runs 20-30% behind the two-stage kernel.
+// whole chunks along i3.  The two-stage kernel (256-byte chunks, returned as
+// 256) needs X already in the operand format; the kernel with C in LDS
+// (returned as 128) takes bf16 X with the bf16 forms and four column waves.
+// Automatic selection takes the kernel with C in LDS where it applies and the
+// row range of a workgroup holds at least one whole 256-row tile (measured at
+// 1024^3 -> 128^3 it runs 15% ahead of the two-stage kernel with bf16x3 and
+// 7% with bf16; with 128-row ranges, as at 256^3 -> 64^3, half of each tile
+// is padding), then the two-stage kernel where X is in the operand format,
+// and the register-staged kernel otherwise.
 template <int MATH, typename XT, int WC>
 static int dma_rowbytes(const SlabArgs &a) {
     typedef typename MathTraits<MATH>::lds_t LT;
     const int mode = slab_kernel_mode();
     if (mode == 1 || !a.x_vec || !aligned(a.X, 16)) return 0;
     const int64_t es = int64_t(sizeof(XT));
-    if (mode == 4) return a.I3 % (256 / es) == 0 ? 1 : 0;   // copy-wave kernel
-    if (mode == 0 || mode == 5) {                            // C through LDS where it applies
+    if (mode == 0 || mode == 3) {                            // C through LDS where it applies
         if constexpr (WC == 4 && (MATH == M_BF16 || MATH == M_BF16X3) && std::is_same<XT, uint16_t>::value)
             if (a.I3 % 64 == 0 && a.ldc % 64 == 0 && a.I3 <= (int64_t(1) << 22) && a.ldc <= (int64_t(1) << 22) &&
                 aligned(a.Chi, 16) && (!a.Clo || aligned(a.Clo, 16)) &&
-                (mode == 5 || a.rows_per_split >= LC_TM))
+                (mode == 3 || a.rows_per_split >= LC_TM))
                 return 128;
-        if (mode == 5) return 0;
+        if (mode == 3) return 0;
     }
     if constexpr (!std::is_same<XT, LT>::value) return 0;
-    if (mode == 3 && a.I3 % (512 / es) == 0) return 512;
     return a.I3 % (256 / es) == 0 ? 256 : 0;
 }
 
 template <int MATH, typename XT, int WC, int NBW, int JB>
 static int launch_slab_dma_rb(const ChainPlan &p, const SlabArgs &a, int rb, hipStream_t st) {
     typedef typename MathTraits<MATH>::lds_t LT;
-    if constexpr (std::is_same<XT, LT>::value) {
-        if (rb == 512) return launch_slab_dma<MATH, WC, NBW, JB, 512>(p, a, st);
-        if (rb == 256) return launch_slab_dma<MATH, WC, NBW, JB, 256>(p, a, st);
-    }
     dim3 grid(unsigned(a.I1 * a.S), unsigned(p.n_j3_tiles), unsigned(p.n_j2_tiles));
+    if constexpr (std::is_same<XT, LT>::value) {
+        if (rb == 256)
+            return launch("ttm_slab", st, [&] {
+                hipLaunchKernelGGL((k_slab_dma<MATH, WC, NBW, JB>), grid, dim3(SLAB_THREADS), 0, st, a);
+            });
+    }
     if constexpr (WC == 4 && (MATH == M_BF16 || MATH == M_BF16X3) && std::is_same<XT, uint16_t>::value) {
         if (rb == 128)
             return launch("ttm_slab", st, [&] {
                 hipLaunchKernelGGL((k_slab_lc<MATH, NBW, JB>), grid, dim3(LC_THREADS), 0, st, a);
             });
     }
-    if (rb != 1) return TTM_ERR_UNSUPPORTED;
-    return launch("ttm_slab", st, [&] {
-        hipLaunchKernelGGL((k_slab_ws<MATH, XT, WC, NBW, JB>), grid, dim3(WS_THREADS), 0, st, a);
-    });
+    return TTM_ERR_UNSUPPORTED;
 }
 
 template <int MATH, typename XT, int WC, int NBW>

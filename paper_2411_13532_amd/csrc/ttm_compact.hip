@@ -436,34 +436,25 @@ int ttm_compact_apply(const int64_t *dims, int mode, const void *X, void *Y, int
     const unsigned row_blocks = unsigned(ceil_div(a.nfib, 256));
     const size_t prep_lds = n <= COMPACT_PREP_LDS_MAX ? size_t(16 * n) : 0;
     {
-        static bool prep_attr[2] = {false, false};
+        static std::atomic<uint64_t> prep_attr[2];
         const int k = dtype == TTM_F64 ? 0 : 1;
-        if (!prep_attr[k]) {
-            const void *fn = dtype == TTM_F64 ? reinterpret_cast<const void *>(&k_compact_prep<double>)
-                                              : reinterpret_cast<const void *>(&k_compact_prep<float>);
-            if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(16 * COMPACT_PREP_LDS_MAX)) !=
-                hipSuccess)
-                return TTM_ERR_HIP;
-            prep_attr[k] = true;
-        }
+        const void *fn = dtype == TTM_F64 ? reinterpret_cast<const void *>(&k_compact_prep<double>)
+                                          : reinterpret_cast<const void *>(&k_compact_prep<float>);
+        if (int rc = ensure_lds_limit(fn, size_t(16 * COMPACT_PREP_LDS_MAX), prep_attr[k])) return rc;
     }
     // mode 3: whole tiles take the prefetching kernel
     const bool full_tiles = n % (dtype == TTM_F64 ? RowsCfg<double>::RT : RowsCfg<float>::RT) == 0;
     if (mode == 3) {
-        static bool attr_set[2][2] = {{false, false}, {false, false}};
+        static std::atomic<uint64_t> attr_set[2][2];
         const int k = dtype == TTM_F64 ? 0 : 1, f = full_tiles ? 1 : 0;
-        if (!attr_set[k][f]) {
-            const void *fn = dtype == TTM_F64
-                                 ? (full_tiles ? reinterpret_cast<const void *>(&k_compact_rows_full<double>)
-                                               : reinterpret_cast<const void *>(&k_compact_rows<double>))
-                                 : (full_tiles ? reinterpret_cast<const void *>(&k_compact_rows_full<float>)
-                                               : reinterpret_cast<const void *>(&k_compact_rows<float>));
-            const int bytes = dtype == TTM_F64 ? int(4 * RowsCfg<double>::WAVE_ELEMS * sizeof(double))
-                                               : int(4 * RowsCfg<float>::WAVE_ELEMS * sizeof(float));
-            if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess)
-                return TTM_ERR_HIP;
-            attr_set[k][f] = true;
-        }
+        const void *fn = dtype == TTM_F64
+                             ? (full_tiles ? reinterpret_cast<const void *>(&k_compact_rows_full<double>)
+                                           : reinterpret_cast<const void *>(&k_compact_rows<double>))
+                             : (full_tiles ? reinterpret_cast<const void *>(&k_compact_rows_full<float>)
+                                           : reinterpret_cast<const void *>(&k_compact_rows<float>));
+        const size_t bytes = dtype == TTM_F64 ? 4 * RowsCfg<double>::WAVE_ELEMS * sizeof(double)
+                                              : 4 * RowsCfg<float>::WAVE_ELEMS * sizeof(float);
+        if (int rc = ensure_lds_limit(fn, bytes, attr_set[k][f])) return rc;
     }
     int rc = TTM_OK;
     if (dtype == TTM_F64) {

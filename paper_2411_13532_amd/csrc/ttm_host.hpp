@@ -2,6 +2,7 @@
 // argument checks, launch bracketing for per-kernel timing, status codes.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <atomic>
 #include <stddef.h>
 #include <stdint.h>
 
@@ -51,12 +52,26 @@ inline int launch(const char *name, hipStream_t s, F &&f) {
     return e == hipSuccess ? TTM_OK : TTM_ERR_HIP;
 }
 
+// Raises the dynamic LDS limit of one kernel for the current device, once per
+// device and process: `done` holds one bit per device id.  Concurrent first
+// calls only set the same attribute twice; a device's bit is published after
+// its call succeeded.
+inline int ensure_lds_limit(const void *kern, size_t lds, std::atomic<uint64_t> &done) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return TTM_ERR_HIP;
+    const uint64_t bit = dev >= 0 && dev < 64 ? uint64_t(1) << dev : 0;
+    if (bit && (done.load(std::memory_order_acquire) & bit)) return TTM_OK;
+    if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)) != hipSuccess)
+        return TTM_ERR_HIP;
+    done.fetch_or(bit, std::memory_order_release);
+    return TTM_OK;
+}
+
 // Number of compute units of the current device (cached per device).
 int device_cu_count();
 
 // Slab-kernel selection set by ttm_set_slab_kernel (0 automatic, 1 register-staged,
-// 2 direct-to-LDS 256-byte chunks, 3 direct-to-LDS 512-byte chunks where possible,
-// 4 direct-to-LDS with a copy wave, 5 X and C through LDS for bf16 X).
+// 2 direct-to-LDS 256-byte chunks, 3 X and C through LDS for bf16 X).
 int slab_kernel_mode();
 
 }  // namespace ttm

@@ -36,9 +36,9 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_slab_kernel_selection_range(lib):
-    for mode in (-1, 6, 100):
+    for mode in (-1, 4, 5, 100):
         assert lib.ttm_set_slab_kernel(mode) == -1
-    for mode in (5, 4, 3, 2, 1, 0):
+    for mode in (3, 2, 1, 0):
         assert lib.ttm_set_slab_kernel(mode) == 0
 
 
@@ -197,3 +197,62 @@ def test_compact_validation_errors(lib):
     assert call(coef=_lib.CompactCoef(1 / 3, 14 / 9, 1 / 9, 0.0)) == _lib.TTM_ERR_INVALID_ARG
     assert call(coef=_lib.CompactCoef(1 / 3, float("nan"), 1 / 9, 0.1)) == _lib.TTM_ERR_INVALID_ARG
     assert lib.ttm_compact_apply(dims, 2, X, Y, _lib.TTM_F64, None, ws, need, 0, None) == _lib.TTM_ERR_INVALID_ARG
+
+
+# ---------------------------------------------------------------------------
+# Failure of the HIP runtime itself.  Where no GPU is visible every HIP call
+# fails, so a fully valid request reaches its first launch (or allocation)
+# and must come back as TTM_ERR_HIP instead of crashing or reporting success.
+# The pointers are well-formed device-looking addresses that no kernel ever
+# receives: the launch itself fails.  Skipped where a GPU is visible.
+# ---------------------------------------------------------------------------
+def _no_gpu():
+    try:
+        import torch
+        return not torch.cuda.is_available()
+    except Exception:
+        return True
+
+
+needs_no_gpu = pytest.mark.skipif(not _no_gpu(), reason="forces HIP failures; only where no GPU is visible")
+FAKE = 1 << 40
+
+
+def fake(k):
+    return ctypes.c_void_p(FAKE + (k << 32))
+
+
+@needs_no_gpu
+@pytest.mark.parametrize("math", ["f64", "f32", "bf16", "bf16x3"])
+def test_launch_failure_maps_to_hip_error(lib, math):
+    m = _lib.MATH[math]
+    fdt = _lib.TTM_F64 if math == "f64" else _lib.TTM_F32
+    xdt = _lib.TTM_BF16 if math in ("bf16", "bf16x3") else fdt
+    s = _lib.shape((64, 300, 128), (16, 20, 40))
+    ws = lib.ttm_chain_workspace_size(ctypes.byref(s), xdt, m)
+    assert ws > 0
+    rc = lib.ttm_chain(ctypes.byref(s), fake(0), xdt, fake(1), fake(2), fake(3), fdt, fake(4), fdt, m,
+                       fake(5), ws, None)
+    assert rc == _lib.TTM_ERR_HIP
+
+
+@needs_no_gpu
+def test_backward_and_copy_failures_map_to_hip_error(lib):
+    s = _lib.shape((32, 64, 64), (8, 8, 8))
+    ws = lib.ttm_chain_backward_workspace_size(ctypes.byref(s), _lib.TTM_F32, _lib.MATH["f32"])
+    rc = lib.ttm_chain_backward(ctypes.byref(s), fake(0), fake(1), fake(2), fake(3), fake(4), _lib.TTM_F32,
+                                fake(5), fake(6), fake(7), fake(8), _lib.MATH["f32"], fake(9), ws, None)
+    assert rc == _lib.TTM_ERR_HIP
+    assert lib.ttm_stream_copy(fake(0), fake(1), 4096, None) == _lib.TTM_ERR_HIP
+
+
+@needs_no_gpu
+def test_plan_create_failure_returns_no_plan(lib):
+    import numpy as np
+    dims = np.array([[5, 6, 7, 5, 6, 7]] * 4, dtype=np.int64)
+    for _ in range(200):       # repeated failures: nothing is handed out
+        h = ctypes.c_void_p(1234)
+        rc = lib.ttm_batched_plan_create(4, dims.ctypes.data_as(ctypes.c_void_p), _lib.TTM_F32, _lib.MATH["f32"],
+                                         None, None, ctypes.byref(h))
+        assert rc == _lib.TTM_ERR_HIP
+        assert h.value is None

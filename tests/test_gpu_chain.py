@@ -3,8 +3,8 @@
 Tolerances (relative Frobenius error against the FP64 oracle on the exact
 stored inputs): 1e-12 for f64, 1e-5 for f32 and bf16x3, 2e-2 for plain bf16.
 Bitwise checks where the arithmetic is exact (identity factors, small
-integers).  Full-size workloads are checked on a sample of output columns
-j3, which the oracle computes exactly as the chain with the sampled rows of C.
+integers).  The full-size workloads compare every output element with the
+oracle's result on the same stored inputs.
 """
 import numpy as np
 import pytest
@@ -169,18 +169,19 @@ def test_compact6_closed_form(n, math):
     if math == "f64":
         assert pins.rel_fro(Y, closed) <= 1e-12
     else:
-        # Forward error bound of a sum of products: |Y^ - Y| <= c u (|A|x|B|x|C|)|X|
-        # with u the relative error of one product (f32: 2^-24 per rounding,
-        # a few roundings per term; bf16x3: 2^-16 from the split and the dropped
-        # lo*lo term) and c = 3 mode products.  cond = ||chain(|X|,|D|..)|| / ||Y||
-        # is large here because D amplifies high wavenumbers while Y is smooth.
+        # Reference: the oracle on the rounded factors.  f32 meets the general
+        # 1e-5.  bf16x3 keeps about 16 significant bits per operand, so its
+        # error is about 2^-17 times the condition number of these sums, which
+        # cancel heavily (D amplifies high wavenumbers while Y is smooth):
+        # cond = ||chain(|X|, |D|, ..)|| / ||Y|| is 10-34 for these sizes and
+        # 3.7e-5 was measured at n = 64.  The fixed cap 1e-4 still fails a
+        # tenfold loss of accuracy.
         Ds32 = [D.astype(np.float32) for D in Ds]
         ref = oracle.chain(stored(Xd), *Ds32)
         cond = np.linalg.norm(oracle.chain(np.abs(stored(Xd)), *(np.abs(D) for D in Ds32))) / np.linalg.norm(ref)
-        u = {"f32": 2.0 ** -21, "bf16x3": 2.0 ** -16}[math]
         err = pins.rel_fro(Y, ref)
         print(f"[compact6 {math} n={n}] rel err {err:.3e}, cond {cond:.1f}", flush=True)
-        assert err <= max(TOL[math], 3 * u * cond)
+        assert err <= {"f32": TOL["f32"], "bf16x3": 1e-4}[math]
 
 
 @pytest.mark.parametrize("math", ["f32", "bf16x3", "bf16", "f64"])
@@ -203,24 +204,23 @@ def test_mode_order_free_operator():
 
 
 # ---------------------------------------------------------------------------
-# Full-size workloads, checked on sampled output columns
+# Full-size workloads: every element of Y against the oracle
 # ---------------------------------------------------------------------------
-def sampled_reference(X_np, A, B, C, cols):
-    """Oracle on Y[:, :, cols] = X x1 A x2 B x3 C[cols, :] (mode 3 first)."""
-    return oracle.chain(X_np, A, B, C[cols, :], order=(3, 2, 1))
-
-
-def test_c2_full_size_fp32():
+@pytest.fixture(scope="module")
+def c2_inputs():
     p = workloads.dense("c2_f32_512_64")
-    Xd = to_dev(p["X"], torch.float32)
-    Y = chain(Xd, to_dev(p["A"], torch.float32), to_dev(p["B"], torch.float32), to_dev(p["C"], torch.float32),
-              math="f32")
-    cols = [0, 1, 31, 63]
-    ref = sampled_reference(p["X"], p["A"].astype(np.float64), p["B"].astype(np.float64),
-                            p["C"].astype(np.float64), cols)
-    err = pins.rel_fro(Y[:, :, cols].double().cpu().numpy(), ref)
-    print(f"[c2 f32] sampled rel err {err:.3e}", flush=True)
-    assert err <= 1e-5
+    dev = [to_dev(p[k], torch.float32) for k in "XABC"]
+    ref = oracle.chain(p["X"], *(p[k].astype(np.float64) for k in "ABC"))
+    return dev, ref
+
+
+@pytest.mark.parametrize("math", ["f32", "bf16x3"])
+def test_c2_full_size(c2_inputs, math):
+    (Xd, Ad, Bd, Cd), ref = c2_inputs
+    Y = chain(Xd, Ad, Bd, Cd, math=math)
+    err = pins.rel_fro(Y.double().cpu().numpy(), ref)
+    print(f"[c2 {math}] rel err {err:.3e}", flush=True)
+    assert err <= TOL[math]
     # orthonormal rows and Gaussian X: entries of Y are N(0,1)
     var = float(Y.double().var().cpu())
     assert abs(var - 1.0) < 0.02
@@ -231,20 +231,36 @@ def c3_inputs():
     p = workloads.dense("c3_bf16_1024_128")
     Xd = p["X"].to(DEV)
     fs = [to_dev(p[k], torch.float32) for k in "ABC"]
-    X_np = p["X"].float().numpy()
-    cols = [0, 77, 127]
-    ref = sampled_reference(X_np, *(p[k].astype(np.float64) for k in "AB"), p["C"].astype(np.float64), cols)
+    X_np = p["X"].float().numpy()          # the stored bf16 values, exactly
+    ref = oracle.chain(X_np, *(p[k].astype(np.float64) for k in "ABC"))
     del X_np
-    return Xd, fs, cols, ref
+    return Xd, fs, ref
 
 
 @pytest.mark.parametrize("math", ["bf16x3", "bf16", "f32"])
 def test_c3_full_size(c3_inputs, math):
-    Xd, fs, cols, ref = c3_inputs
+    Xd, fs, ref = c3_inputs
     Y = chain(Xd, *fs, math=math)
-    err = pins.rel_fro(Y[:, :, cols].double().cpu().numpy(), ref)
-    print(f"[c3 {math}] sampled rel err {err:.3e}", flush=True)
+    err = pins.rel_fro(Y.double().cpu().numpy(), ref)
+    print(f"[c3 {math}] rel err {err:.3e}", flush=True)
     assert err <= TOL[math]
+
+
+# ---------------------------------------------------------------------------
+# The automatic selection on bf16 X with ragged multi-tile row ranges: several
+# 256-row tiles per workgroup with a partial last tile, 384-row ranges over
+# two splits, and one or two 64-value chunks per row (the short-row preamble).
+# ---------------------------------------------------------------------------
+LC_SHAPES = [((1024, 300, 64), (24, 40, 100)), ((512, 600, 128), (33, 40, 70)), ((1024, 600, 64), (16, 20, 48))]
+
+
+@pytest.mark.parametrize("form", FORMS, ids=FORM_IDS)
+@pytest.mark.parametrize("shape", LC_SHAPES, ids=lambda s: f"I{s[0]}J{s[1]}")
+def test_chain_multi_tile_ranges(form, shape):
+    math, xdt = form
+    I, J = shape
+    p = workloads.random_problem(I, J, seed=sum(I) + 3 * sum(J))
+    check_vs_oracle(p, math, xdt)
 
 
 # ---------------------------------------------------------------------------
@@ -264,7 +280,7 @@ def slab_kernel_mode():
     set_slab_kernel(0)
 
 
-@pytest.mark.parametrize("mode", [0, 1, 2, 3, 4, 5], ids=["auto", "staged", "dma256", "dma512", "copywave", "ldsc"])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3], ids=["auto", "staged", "dma256", "ldsc"])
 @pytest.mark.parametrize("form", [("f64", None), ("f32", None), ("bf16", torch.bfloat16), ("bf16x3", torch.bfloat16)],
                          ids=["f64", "f32", "bf16", "bf16x3"])
 @pytest.mark.parametrize("shape", DMA_SHAPES, ids=lambda s: f"I{s[0]}J{s[1]}")
@@ -283,7 +299,7 @@ def test_slab_kernels_identity_bitwise(form, slab_kernel_mode):
     I = (3, 200, 256)
     X = torch.from_numpy(rng.standard_normal(I).astype(np.float32)).to(torch.bfloat16).float().numpy()
     outs = []
-    for mode in (0, 1, 2, 3, 4, 5):
+    for mode in (0, 1, 2, 3):
         slab_kernel_mode(mode)
         Y, Xd = run(X, *[np.eye(n) for n in I], math, xdt)
         assert np.array_equal(Y, stored(Xd).astype(np.float64))
