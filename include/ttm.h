@@ -143,6 +143,32 @@ int ttm_chain(const ttm_shape *shape,
               void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * computation and results as ttm_chain (the same kernels, bit for bit), with
+ * the workspace taken from a scratch array the library holds on each GPU
+ * instead of a caller buffer.  The call itself allocates nothing.
+ *
+ * Scratch: TTM_NOALLOC_SCRATCH_BYTES bytes of device memory per GPU, part of
+ * the library's device code (it exists on a GPU once the library's kernels
+ * are loaded there, and is held until the process ends).  Shapes whose
+ * ttm_chain_workspace_size exceeds it return TTM_ERR_WORKSPACE (the
+ * 1024^3 -> 128^3 bf16x3 chain needs about 82 MiB and must use ttm_chain;
+ * 512^3 -> 64^3 fits).  The first call on a GPU looks up the array's device
+ * address (no allocation); make that first call outside graph capture.
+ *
+ * Every call on one GPU uses the same scratch: calls that overlap in time on
+ * one GPU (on different streams, or from different threads without
+ * ordering) race and give wrong results.  Calls ordered on one stream are
+ * safe.  Arguments, layout and errors otherwise as for ttm_chain.
+ */
+#define TTM_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int ttm_chain_noalloc(const ttm_shape *shape,
+                      const void *X, int x_dtype,
+                      const void *A, const void *B, const void *C, int f_dtype,
+                      void *Y, int y_dtype, int math, void *stream);
+
+/*
  * Gradient of a scalar loss L through the chain, given G = dL/dY:
  *     dX = G x1 A^T x2 B^T x3 C^T
  *     dA[j1,i1] = sum_{j2,j3} G[j1,j2,j3] (X x2 B x3 C)[i1,j2,j3]

@@ -20,6 +20,7 @@ TTM_ERR_ALIAS = -4
 TTM_ERR_HIP = -5
 
 TTM_F64, TTM_F32, TTM_BF16 = 0, 1, 2
+TTM_NOALLOC_SCRATCH_BYTES = 64 << 20
 MATH = {"f64": 0, "f32": 1, "bf16": 2, "bf16x3": 3}
 
 # every exported entry point and its C signature
@@ -47,6 +48,7 @@ SIGNATURES = {
     "ttm_chain_supported": (INT, [INT, INT, INT, INT]),
     "ttm_chain_workspace_size": (SZ, [PShape, INT, INT]),
     "ttm_chain": (INT, [PShape, P, INT, P, P, P, INT, P, INT, INT, P, SZ, P]),
+    "ttm_chain_noalloc": (INT, [PShape, P, INT, P, P, P, INT, P, INT, INT, P]),
     "ttm_chain_backward_workspace_size": (SZ, [PShape, INT, INT]),
     "ttm_chain_backward": (INT, [PShape, P, P, P, P, P, INT, P, P, P, P, INT, P, SZ, P]),
     "ttm_batched_plan_create": (INT, [I64, P, INT, INT, ctypes.c_char_p, P, ctypes.POINTER(P)]),

@@ -16,6 +16,7 @@
 //      (no atomics, so every call is bitwise reproducible).
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 #include <type_traits>
 #include <utility>
 
@@ -1527,6 +1528,75 @@ static int validate_shape(const ttm_shape *s) {
     return TTM_OK;
 }
 
+// Argument checks shared by the entry points of the chain (everything but
+// the workspace) and the plan for the shape.
+static int chain_check(const ttm_shape *s, const void *X, int x_dtype, const void *A, const void *B,
+                       const void *C, int f_dtype, const void *Y, int y_dtype, int math, ChainPlan &p) {
+    int rc = validate_shape(s);
+    if (rc) return rc;
+    if (!combo_ok(x_dtype, f_dtype, y_dtype, math)) return TTM_ERR_UNSUPPORTED;
+    if (!X || !A || !B || !C || !Y) return TTM_ERR_INVALID_ARG;
+    const size_t fs = dtype_size(f_dtype), ys = dtype_size(y_dtype), xs = dtype_size(x_dtype);
+    if (!aligned(X, 16) || !aligned(Y, 16) || !aligned(A, fs) || !aligned(B, fs) || !aligned(C, fs))
+        return TTM_ERR_INVALID_ARG;
+    if (!make_plan(*s, x_dtype, math, p)) return TTM_ERR_UNSUPPORTED;
+    const size_t ny = size_t(s->J[0] * s->J[1] * s->J[2]) * ys;
+    const size_t nx = size_t(s->I[0] * s->I[1] * s->I[2]) * xs;
+    if (overlaps(Y, ny, X, nx) || overlaps(Y, ny, A, size_t(s->J[0] * s->I[0]) * fs) ||
+        overlaps(Y, ny, B, size_t(s->J[1] * s->I[1]) * fs) || overlaps(Y, ny, C, size_t(s->J[2] * s->I[2]) * fs))
+        return TTM_ERR_ALIAS;
+    return TTM_OK;
+}
+
+// Workspace checks and the launches.
+static int chain_run(const ChainPlan &p, const ttm_shape *s, const void *X, const void *A, const void *B,
+                     const void *C, void *Y, int math, void *ws, size_t ws_bytes, hipStream_t st) {
+    if (!ws || ws_bytes < p.total) return TTM_ERR_WORKSPACE;
+    if (!aligned(ws, 16)) return TTM_ERR_INVALID_ARG;
+    const size_t fs = p.math == TTM_MATH_F64 ? 8 : 4, ys = fs, xs = dtype_size(p.xdt);
+    const size_t ny = size_t(s->J[0] * s->J[1] * s->J[2]) * ys;
+    const size_t nx = size_t(s->I[0] * s->I[1] * s->I[2]) * xs;
+    if (overlaps(Y, ny, ws, p.total) || overlaps(ws, p.total, X, nx) ||
+        overlaps(ws, p.total, A, size_t(s->J[0] * s->I[0]) * fs) ||
+        overlaps(ws, p.total, B, size_t(s->J[1] * s->I[1]) * fs) ||
+        overlaps(ws, p.total, C, size_t(s->J[2] * s->I[2]) * fs))
+        return TTM_ERR_ALIAS;
+    unsigned char *w = static_cast<unsigned char *>(ws);
+    switch (math) {
+        case TTM_MATH_F64: return run_chain<M_F64>(p, *s, X, A, B, C, Y, w, st);
+        case TTM_MATH_F32: return run_chain<M_F32>(p, *s, X, A, B, C, Y, w, st);
+        case TTM_MATH_BF16: return run_chain<M_BF16>(p, *s, X, A, B, C, Y, w, st);
+        case TTM_MATH_BF16X3: return run_chain<M_BF16X3>(p, *s, X, A, B, C, Y, w, st);
+        default: return TTM_ERR_UNSUPPORTED;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Library-owned scratch for ttm_chain_noalloc: a fixed device array in this
+// code object, one copy per GPU, held until the process ends.  Host code
+// never uses the array's name as an address (on the host it names a
+// stand-in); the device address comes from hipGetSymbolAddress, taken once
+// per device with that device current and kept per device.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[TTM_NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[64];
+
+static int noalloc_scratch(void **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return TTM_ERR_HIP;
+    if (dev < 0 || dev >= 64) return TTM_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return TTM_ERR_HIP;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return TTM_OK;
+}
+
 }  // namespace ttm
 
 using namespace ttm;
@@ -1546,36 +1616,22 @@ size_t ttm_chain_workspace_size(const ttm_shape *s, int x_dtype, int math) {
 
 int ttm_chain(const ttm_shape *s, const void *X, int x_dtype, const void *A, const void *B, const void *C,
               int f_dtype, void *Y, int y_dtype, int math, void *ws, size_t ws_bytes, void *stream) {
-    int rc = validate_shape(s);
-    if (rc) return rc;
-    if (!combo_ok(x_dtype, f_dtype, y_dtype, math)) return TTM_ERR_UNSUPPORTED;
-    if (!X || !A || !B || !C || !Y) return TTM_ERR_INVALID_ARG;
-    const size_t fs = dtype_size(f_dtype), ys = dtype_size(y_dtype), xs = dtype_size(x_dtype);
-    if (!aligned(X, 16) || !aligned(Y, 16) || !aligned(A, fs) || !aligned(B, fs) || !aligned(C, fs))
-        return TTM_ERR_INVALID_ARG;
     ChainPlan p;
-    if (!make_plan(*s, x_dtype, math, p)) return TTM_ERR_UNSUPPORTED;
-    if (!ws || ws_bytes < p.total) return TTM_ERR_WORKSPACE;
-    if (!aligned(ws, 16)) return TTM_ERR_INVALID_ARG;
-    const size_t ny = size_t(s->J[0] * s->J[1] * s->J[2]) * ys;
-    const size_t nx = size_t(s->I[0] * s->I[1] * s->I[2]) * xs;
-    if (overlaps(Y, ny, X, nx) || overlaps(Y, ny, A, size_t(s->J[0] * s->I[0]) * fs) ||
-        overlaps(Y, ny, B, size_t(s->J[1] * s->I[1]) * fs) || overlaps(Y, ny, C, size_t(s->J[2] * s->I[2]) * fs) ||
-        overlaps(Y, ny, ws, p.total))
-        return TTM_ERR_ALIAS;
-    if (overlaps(ws, p.total, X, nx) || overlaps(ws, p.total, A, size_t(s->J[0] * s->I[0]) * fs) ||
-        overlaps(ws, p.total, B, size_t(s->J[1] * s->I[1]) * fs) ||
-        overlaps(ws, p.total, C, size_t(s->J[2] * s->I[2]) * fs))
-        return TTM_ERR_ALIAS;
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    unsigned char *w = static_cast<unsigned char *>(ws);
-    switch (math) {
-        case TTM_MATH_F64: return run_chain<M_F64>(p, *s, X, A, B, C, Y, w, st);
-        case TTM_MATH_F32: return run_chain<M_F32>(p, *s, X, A, B, C, Y, w, st);
-        case TTM_MATH_BF16: return run_chain<M_BF16>(p, *s, X, A, B, C, Y, w, st);
-        case TTM_MATH_BF16X3: return run_chain<M_BF16X3>(p, *s, X, A, B, C, Y, w, st);
-        default: return TTM_ERR_UNSUPPORTED;
-    }
+    int rc = chain_check(s, X, x_dtype, A, B, C, f_dtype, Y, y_dtype, math, p);
+    if (rc) return rc;
+    return chain_run(p, s, X, A, B, C, Y, math, ws, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+int ttm_chain_noalloc(const ttm_shape *s, const void *X, int x_dtype, const void *A, const void *B,
+                      const void *C, int f_dtype, void *Y, int y_dtype, int math, void *stream) {
+    ChainPlan p;
+    int rc = chain_check(s, X, x_dtype, A, B, C, f_dtype, Y, y_dtype, math, p);
+    if (rc) return rc;
+    if (p.total > TTM_NOALLOC_SCRATCH_BYTES) return TTM_ERR_WORKSPACE;
+    void *ws = nullptr;
+    rc = noalloc_scratch(&ws);
+    if (rc) return rc;
+    return chain_run(p, s, X, A, B, C, Y, math, ws, TTM_NOALLOC_SCRATCH_BYTES, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

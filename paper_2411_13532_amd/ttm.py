@@ -79,6 +79,30 @@ def chain(X: torch.Tensor, A: torch.Tensor, B: torch.Tensor, C: torch.Tensor, ma
     return out
 
 
+def chain_noalloc(X: torch.Tensor, A: torch.Tensor, B: torch.Tensor, C: torch.Tensor, math: str = "f32",
+                  out: torch.Tensor | None = None) -> torch.Tensor:
+    """ttm_chain_noalloc: as :func:`chain`, with the library's per-GPU scratch
+    as workspace (no workspace allocation; `out` may be given to allocate
+    nothing at all)."""
+    _need_cuda(X, A, B, C, out)
+    if X.dim() != 3 or A.dim() != 2 or B.dim() != 2 or C.dim() != 2:
+        raise ValueError("X must be 3-way and A, B, C matrices")
+    I = tuple(X.shape)
+    J = (A.shape[0], B.shape[0], C.shape[0])
+    if (A.shape[1], B.shape[1], C.shape[1]) != I:
+        raise ValueError(f"factor widths {A.shape[1], B.shape[1], C.shape[1]} do not match X {I}")
+    if B.dtype != A.dtype or C.dtype != A.dtype:
+        raise ValueError("A, B and C must share one dtype")
+    m = _math_id(math)
+    if out is None:
+        out = torch.empty(J, dtype=torch.float64 if math == "f64" else torch.float32, device=X.device)
+    s = _lib.shape(I, J)
+    rc = _lib.load().ttm_chain_noalloc(ctypes.byref(s), _ptr(X), _DT.get(X.dtype, -1), _ptr(A), _ptr(B), _ptr(C),
+                                       _DT.get(A.dtype, -1), _ptr(out), _DT.get(out.dtype, -1), m, _stream(X.device))
+    check(rc, "ttm_chain_noalloc")
+    return out
+
+
 def chain_backward_workspace_size(I, J, dtype: torch.dtype, math: str) -> int:
     s = _lib.shape(I, J)
     return int(_lib.load().ttm_chain_backward_workspace_size(ctypes.byref(s), _DT[dtype], _math_id(math)))
