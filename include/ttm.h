@@ -189,7 +189,10 @@ int ttm_chain_backward(const ttm_shape *shape, const void *G,
 
 /*
  * Batched chains over `count` independent cuboids (ragged sizes), run by one
- * persistent kernel launch.
+ * persistent kernel launch.  One wavefront takes one cuboid at a time with
+ * one lane per fiber of each mode (the paper's grouping of independent lines
+ * onto the lanes of one unit, Sec. 4.1); cuboids are dealt to the waves
+ * longest first, each to the wave with the least work so far (LPT).
  *
  * dims_host : host array of count x 6 int64, per cuboid (I1,I2,I3,J1,J2,J3),
  *             every entry in [1, 16].
@@ -201,8 +204,9 @@ int ttm_chain_backward(const ttm_shape *shape, const void *G,
  *             cuboid order (each row-major as in ttm_chain); cuboid k starts at
  *             the running sum of the element counts of cuboids 0..k-1.
  *             ttm_batched_plan_totals reports the total element counts.
- * Creating a plan allocates host memory and a small device metadata buffer
- * and copies the metadata synchronously on `stream`; destroy frees both.
+ * Creating a plan allocates host memory and device metadata (the cuboid
+ * descriptors in the order the waves take them, and each wave's first
+ * entry) and copies it synchronously on `stream`; destroy frees both.
  */
 int ttm_batched_plan_create(int64_t count, const int64_t *dims_host, int dtype, int math,
                             const char *tune_cache, void *stream, ttm_batched_plan **out);
@@ -233,18 +237,23 @@ int ttm_chain_batched_loop(const ttm_batched_plan *plan, const void *X, const vo
                            const void *B, const void *C, void *Y, void *stream);
 
 /*
- * Autotune the batched launch shape: times every candidate (block size,
- * resident blocks per compute unit) on the given buffers with HIP events,
- * keeps the fastest in the plan, and, when the plan has a tune_cache path,
- * rewrites that JSON file.  Synchronises `stream`.  Y is overwritten.
- * best_out (nullable) receives the chosen candidate's mean time in ms.
+ * Autotune the batched launch: times every candidate (kernel variant, block
+ * size, resident blocks per compute unit) on the given buffers with HIP
+ * events, each timed launch on a cold last-level cache (a 512 MiB buffer the
+ * call allocates is rewritten before it), rebuilds the LPT assignment for
+ * each candidate's wave count, keeps the fastest in the plan, and, when the
+ * plan has a tune_cache path, rewrites that JSON file.  Synchronises
+ * `stream`.  Y is overwritten.  best_ms_out (nullable) receives the chosen
+ * candidate's mean time in ms.
  */
 int ttm_batched_autotune(ttm_batched_plan *plan, const void *X, const void *A,
                          const void *B, const void *C, void *Y, void *stream,
                          int reps, double *best_ms_out);
 
-/* The plan's current launch shape: out[0] = threads per block, out[1] =
- * blocks per compute unit, out[2] = total blocks. */
+/* The plan's current launch shape (out holds 4 ints): out[0] = threads per
+ * block, out[1] = resident blocks per compute unit, out[2] = total blocks,
+ * out[3] = kernel variant (float: 0 keeps the next cuboid's inputs in
+ * registers at two waves per SIMD, 1 runs three waves per SIMD without). */
 int ttm_batched_plan_config(const ttm_batched_plan *plan, int *out);
 
 /*

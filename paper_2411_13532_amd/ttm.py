@@ -214,9 +214,9 @@ class BatchedPlan:
         return best.value
 
     def config(self):
-        out = (ctypes.c_int * 3)()
+        out = (ctypes.c_int * 4)()
         check(self._lib.ttm_batched_plan_config(self._h, out), "ttm_batched_plan_config")
-        return {"threads": out[0], "blocks_per_cu": out[1], "blocks": out[2]}
+        return {"threads": out[0], "blocks_per_cu": out[1], "blocks": out[2], "variant": out[3]}
 
 
 COMPACT6 = (1.0 / 3.0, 14.0 / 9.0, 1.0 / 9.0)   # alpha, a, b of Sec. 4.2 Eq. (cfds)
