@@ -67,6 +67,8 @@ def _load():
         lib.ttmo_compact6_apply.argtypes = [ctypes.c_int, P] + [ctypes.c_double] * 4 + [P, P]
         lib.ttmo_compact6_apply.restype = ctypes.c_int
         lib.ttmo_batched.restype = ctypes.c_int
+        lib.ttmo_reorder.argtypes = [P, P, P, P, ctypes.c_int, ctypes.c_int]
+        lib.ttmo_reorder.restype = ctypes.c_int
         for name in ("ttmo_thomas", "ttmo_thomas_periodic"):
             getattr(lib, name).argtypes = [ctypes.c_int64] + [P] * 5
             getattr(lib, name).restype = ctypes.c_int
@@ -208,4 +210,29 @@ def compact6_apply(X, mode: int, alpha: float, a: float, b: float, h: float) -> 
                                      float(h), _ptr(Xc), _ptr(out))
     if rc != 0:
         raise ValueError("compact6_apply needs mode in 1..3 and at least 3 points along it")
+    return out
+
+
+def reorder(X, perm, Y=None) -> np.ndarray:
+    """X (3-way, float32 or float64) with its axes permuted, Y's axis k being
+    X's axis perm[k] (Sec. 4.1's move between directional layouts), moved as
+    bytes; with Y given, Y + that in X's dtype (returned as a new array)."""
+    X = np.ascontiguousarray(X)
+    if X.ndim != 3 or X.dtype not in (np.float32, np.float64):
+        raise ValueError("X must be a 3-way float32 or float64 array")
+    p = np.ascontiguousarray(np.asarray(perm, dtype=np.int32))
+    if sorted(int(k) for k in p) != [0, 1, 2]:
+        raise ValueError("perm must be a permutation of (0, 1, 2)")
+    yshape = tuple(X.shape[int(k)] for k in p)
+    if Y is None:
+        out = np.empty(yshape, dtype=X.dtype)
+        acc = 0
+    else:
+        out = np.array(Y, dtype=X.dtype, copy=True, order="C")
+        if out.shape != yshape:
+            raise ValueError("Y has the wrong shape")
+        acc = 1
+    rc = _load().ttmo_reorder(_ptr(_i64(X.shape)), _ptr(p), _ptr(X), _ptr(out), X.dtype.itemsize, acc)
+    if rc != 0:
+        raise ValueError("perm must be a permutation of (0, 1, 2)")
     return out

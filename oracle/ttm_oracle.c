@@ -407,3 +407,51 @@ int ttmo_compact6_apply(int mode, const int64_t *dims, double alpha, double a, d
     }
     return rc ? -1 : 0;
 }
+
+/* ---------------------------------------------------------------------------
+ * Reordering a field between directional layouts (Sec. 4.1: each direction
+ * has its own layout, and a reorder moves a field from one to another;
+ * Sec. 5.3 counts these moves in the transport equation's data movement).
+ * For a 3-way array X of dims (n0, n1, n2) and a permutation perm of
+ * {0, 1, 2}, Y's axis k is X's axis perm[k]:
+ *   Y[i_perm[0]][i_perm[1]][i_perm[2]] = X[i0][i1][i2],
+ * Y of dims (n_perm[0], n_perm[1], n_perm[2]).  Elements are es bytes (4:
+ * float, 8: double) and are moved as bytes, so the result is bit-exact.
+ * accumulate != 0: Y += that instead (the accumulation of a direction's
+ * result into another layout), the sum taken in double and rounded to the
+ * element type, which is the correctly rounded sum of the two stored values.
+ * ------------------------------------------------------------------------- */
+int ttmo_reorder(const int64_t *dims, const int *perm, const void *X, void *Y, int es, int accumulate)
+{
+    if (es != 4 && es != 8) return -1;
+    int seen[3] = {0, 0, 0};
+    for (int k = 0; k < 3; ++k) {
+        if (perm[k] < 0 || perm[k] > 2 || seen[perm[k]]) return -1;
+        seen[perm[k]] = 1;
+    }
+    const int64_t yd[3] = {dims[perm[0]], dims[perm[1]], dims[perm[2]]};
+    const unsigned char *xb = (const unsigned char *)X;
+    unsigned char *yb = (unsigned char *)Y;
+#pragma omp parallel for schedule(static)
+    for (int64_t i0 = 0; i0 < dims[0]; ++i0) {
+        int64_t idx[3];
+        idx[0] = i0;
+        for (idx[1] = 0; idx[1] < dims[1]; ++idx[1]) {
+            for (idx[2] = 0; idx[2] < dims[2]; ++idx[2]) {
+                const int64_t src = (idx[0] * dims[1] + idx[1]) * dims[2] + idx[2];
+                const int64_t dst = (idx[perm[0]] * yd[1] + idx[perm[1]]) * yd[2] + idx[perm[2]];
+                if (!accumulate) {
+                    memcpy(yb + dst * es, xb + src * es, (size_t)es);
+                } else if (es == 4) {
+                    float *y = (float *)(yb + dst * 4);
+                    const float x = *(const float *)(xb + src * 4);
+                    *y = (float)((double)*y + (double)x);
+                } else {
+                    double *y = (double *)(yb + dst * 8);
+                    *y = *y + *(const double *)(xb + src * 8);
+                }
+            }
+        }
+    }
+    return 0;
+}

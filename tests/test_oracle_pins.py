@@ -367,3 +367,58 @@ def test_compact_planted_mistakes_are_caught(mutant):
 def test_oracle_compact_apply_rejects_short_fibers():
     with pytest.raises(ValueError):
         oracle.compact6_apply(np.zeros((2, 4, 4)), 1, 1 / 3, 14 / 9, 1 / 9, 0.1)
+
+
+# ---------------------------------------------------------------------------
+# Reordering between directional layouts (Sec. 4.1) and accumulation
+# ---------------------------------------------------------------------------
+import itertools
+
+PERMS = list(itertools.permutations(range(3)))
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_reorder_matches_numpy_transpose(dtype):
+    rng = np.random.default_rng(61)
+    X = rng.standard_normal((5, 7, 9)).astype(dtype)
+    for perm in PERMS:
+        Y = oracle.reorder(X, perm)
+        assert Y.dtype == dtype and Y.shape == tuple(X.shape[k] for k in perm)
+        assert np.array_equal(Y.view(np.uint8), np.ascontiguousarray(np.transpose(X, perm)).view(np.uint8)), perm
+
+
+def test_reorder_inverse_and_composition_bitwise():
+    rng = np.random.default_rng(62)
+    X = rng.standard_normal((4, 6, 3))
+    for p in PERMS:
+        inv = tuple(int(i) for i in np.argsort(p))
+        assert np.array_equal(oracle.reorder(oracle.reorder(X, p), inv), X)
+        for q in PERMS:
+            # Y = reorder(X, p) has axis k = X axis p[k]; reordering Y by q
+            # gives axis k = Y axis q[k] = X axis p[q[k]]
+            pq = tuple(p[q[k]] for k in range(3))
+            assert np.array_equal(oracle.reorder(oracle.reorder(X, p), q), oracle.reorder(X, pq))
+
+
+def test_reorder_keeps_nan_and_signed_zero_bits():
+    X = np.array([np.nan, -0.0, np.inf, 1.0, -np.inf, 0.0], dtype=np.float32).reshape(1, 2, 3)
+    Y = oracle.reorder(X, (2, 0, 1))
+    assert np.array_equal(Y.view(np.uint32), np.transpose(X, (2, 0, 1)).copy().view(np.uint32))
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_accumulate_is_the_rounded_sum(dtype):
+    rng = np.random.default_rng(63)
+    X = rng.standard_normal((3, 8, 5)).astype(dtype)
+    for perm in PERMS:
+        Y0 = rng.standard_normal(tuple(X.shape[k] for k in perm)).astype(dtype)
+        Y = oracle.reorder(X, perm, Y=Y0)
+        # the sum in the element type (numpy adds float32 arrays in float32)
+        assert np.array_equal(Y, Y0 + np.transpose(X, perm)), perm
+
+
+def test_reorder_rejects_bad_perm():
+    X = np.zeros((2, 2, 2))
+    for bad in [(0, 0, 1), (0, 1, 3), (-1, 1, 2)]:
+        with pytest.raises(ValueError):
+            oracle.reorder(X, bad)
