@@ -20,7 +20,8 @@ timed steps (one HIP event after each step on the stream).
 Other workloads: --workload c2 (X 512^3 float32, J = 64, float32),
 c4 (20000 ragged cuboids), c5 (X 256^3 float32, J = 32, forward + adjoint),
 c6 (compact sixth-order derivative sweeps along each mode of a 512^3
-float64 field).
+float64 field), reorder (moves of a 512^3 float64 field between
+directional layouts).
 """
 from __future__ import annotations
 
@@ -373,12 +374,48 @@ def bench_c6(args, torch, ttm):
             "per_mode": per_mode}
 
 
+def bench_reorder(args, torch, ttm):
+    """Moves of a 512^3 float64 field between directional layouts (Sec. 4.1)
+    and the accumulating form; algorithmic bytes: read X and write Y once
+    (accumulate: also read Y)."""
+    I = 512
+    dev = "cuda:0"
+    g = torch.Generator(device=dev)
+    g.manual_seed(7)
+    X = torch.randn((I, I, I), dtype=torch.float64, device=dev, generator=g)
+    Y = torch.empty_like(X)
+    nb = X.numel() * 8
+    res = {}
+    for name, perm, acc in (("xy_swap_inner", (0, 2, 1), False), ("xz_swap", (2, 1, 0), False),
+                            ("outer_swap", (1, 0, 2), False), ("cycle", (1, 2, 0), False),
+                            ("xz_swap_accumulate", (2, 1, 0), True)):
+        fn = lambda: ttm.reorder(X, perm, out=Y, accumulate=acc)
+        ms = timed(fn, args.steps, args.warmup, torch)["median"]
+        kms = kernel_times(fn, args.steps, torch, ttm)["ttm_reorder"][1]
+        bytes_ = (3 if acc else 2) * nb
+        res[name] = {"perm": perm, "accumulate": acc, "ms": round(ms, 4), "kernel_ms": round(kms, 4),
+                     "gbs": round(bytes_ / (kms * 1e-3) / 1e9, 1)}
+    worst = min(res.values(), key=lambda v: v["gbs"])
+    copy = copy_gbs(torch, ttm, 1 << 30, 10)
+    main = res["xz_swap"]
+    return {"metric": "layout reorder GB/s (read + write)", "value": main["gbs"], "unit": "GB/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": main["ms"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "X 512^3 float64 N(0,1); Y = X with axes 0 and 2 exchanged (perm (2, 1, 0))",
+                       "I": I},
+            "roofline": {"bound": "hbm", "achieved": main["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(main["gbs"] / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "ttm_reorder",
+                         "kernel_ms": main["kernel_ms"], "copy_ceiling_gbs": round(copy, 1),
+                         "slowest_perm_gbs": worst["gbs"]},
+            "per_perm": res}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c4", "c5", "c6", "copy"])
+    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c4", "c5", "c6", "copy", "reorder"])
     ap.add_argument("--forms", default="bf16x3,f32,bf16",
                     help="c3: arithmetic forms to run (bf16x3 is the headline and must be included)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -393,7 +430,8 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.init()
-    fn = {"c3": bench_dense_precision, "c2": bench_c2, "c4": bench_c4, "c5": bench_c5, "c6": bench_c6, "copy": bench_copy}[args.workload]
+    fn = {"c3": bench_dense_precision, "c2": bench_c2, "c4": bench_c4, "c5": bench_c5, "c6": bench_c6, "copy": bench_copy,
+          "reorder": bench_reorder}[args.workload]
     line = fn(args, torch, ttm)
     print(json.dumps(line), flush=True)
 

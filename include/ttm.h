@@ -301,6 +301,27 @@ int ttm_compact_apply(const int64_t *dims, int mode, const void *X, void *Y, int
                       const ttm_compact_coef *coef, void *ws, size_t ws_bytes, int prepared, void *stream);
 
 /*
+ * A field moved between directional layouts (Sec. 4.1: each direction has
+ * its own layout, in which that direction's lines are contiguous, and Sec.
+ * 5.3 counts these reorders in the data movement of a transport step):
+ *
+ *   Y[i_perm[0]][i_perm[1]][i_perm[2]] = X[i0][i1][i2]      (accumulate = 0)
+ *   Y[i_perm[0]][i_perm[1]][i_perm[2]] += X[i0][i1][i2]     (accumulate != 0)
+ *
+ * i.e. Y's axis k is X's axis perm[k]; the accumulating form adds a
+ * direction's result into another layout, in the element type.
+ *   dims   host array (n0, n1, n2) of X, each in [1, 2^31]
+ *   perm   host array, a permutation of {0, 1, 2}
+ *   X, Y   device, row-major, dtype F32 or F64, aligned to the element size;
+ *          Y has dims (n_perm[0], n_perm[1], n_perm[2]) and must not overlap X
+ * The copy is bit-exact (elements move as bytes).  Errors:
+ * TTM_ERR_INVALID_ARG (null pointer, sizes, perm, misalignment),
+ * TTM_ERR_UNSUPPORTED (dtype, grid limits), TTM_ERR_ALIAS, TTM_ERR_HIP.
+ */
+int ttm_reorder(const int64_t *dims, const int *perm, const void *X, void *Y, int dtype, int accumulate,
+                void *stream);
+
+/*
  * Plain device-to-device copy of `bytes` (a multiple of 16; both pointers
  * 16-byte aligned, not overlapping) on `stream`: the practical HBM bandwidth
  * ceiling for the roofline, and the known-size reference for byte counters.

@@ -290,3 +290,28 @@ def timing_collect(max_entries: int = 32) -> dict:
         name = names.raw[64 * k:64 * k + 64].split(b"\0", 1)[0].decode()
         out[name] = (int(counts[k]), float(ms[k]))
     return out
+
+
+def reorder(X: torch.Tensor, perm, out: torch.Tensor | None = None, accumulate: bool = False) -> torch.Tensor:
+    """ttm_reorder: X (3-way, float32 or float64) moved to the layout whose
+    axis k is X's axis perm[k] (a directional layout change, Sec. 4.1); with
+    accumulate=True the result is added to `out` instead of written."""
+    _need_cuda(X, out)
+    if X.dim() != 3 or X.dtype not in (torch.float32, torch.float64):
+        raise ValueError("X must be a 3-way float32 or float64 tensor")
+    import numpy as np
+    p = np.ascontiguousarray(np.asarray(perm, dtype=np.int32))
+    if sorted(int(k) for k in p) != [0, 1, 2]:
+        raise ValueError("perm must be a permutation of (0, 1, 2)")
+    yshape = tuple(X.shape[int(k)] for k in p)
+    if out is None:
+        if accumulate:
+            raise ValueError("accumulate needs out")
+        out = torch.empty(yshape, dtype=X.dtype, device=X.device)
+    elif tuple(out.shape) != yshape or out.dtype != X.dtype:
+        raise ValueError("out has the wrong shape or dtype")
+    dims = np.ascontiguousarray(np.asarray(X.shape, dtype=np.int64))
+    rc = _lib.load().ttm_reorder(dims.ctypes.data_as(ctypes.c_void_p), p.ctypes.data_as(ctypes.c_void_p), _ptr(X),
+                                 _ptr(out), _DT[X.dtype], int(bool(accumulate)), _stream(X.device))
+    check(rc, "ttm_reorder")
+    return out
