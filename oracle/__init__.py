@@ -67,6 +67,8 @@ def _load():
         lib.ttmo_compact6_apply.argtypes = [ctypes.c_int, P] + [ctypes.c_double] * 4 + [P, P]
         lib.ttmo_compact6_apply.restype = ctypes.c_int
         lib.ttmo_batched.restype = ctypes.c_int
+        lib.ttmo_gram.argtypes = [P, ctypes.c_int, P, P]
+        lib.ttmo_gram.restype = ctypes.c_int
         lib.ttmo_reorder.argtypes = [P, P, P, P, ctypes.c_int, ctypes.c_int]
         lib.ttmo_reorder.restype = ctypes.c_int
         for name in ("ttmo_thomas", "ttmo_thomas_periodic"):
@@ -236,3 +238,40 @@ def reorder(X, perm, Y=None) -> np.ndarray:
     if rc != 0:
         raise ValueError("perm must be a permutation of (0, 1, 2)")
     return out
+
+
+def gram(X, mode: int) -> np.ndarray:
+    """G = X_(mode) X_(mode)^T in float64 (plain loops)."""
+    Xc = _f64(X)
+    n = Xc.shape[mode - 1]
+    G = np.empty((n, n), dtype=np.float64)
+    if _load().ttmo_gram(_ptr(_i64(Xc.shape)), int(mode), _ptr(Xc), _ptr(G)) != 0:
+        raise ValueError("mode must be 1, 2 or 3")
+    return G
+
+
+def sign_fixed_rows(U: np.ndarray) -> np.ndarray:
+    """Each row multiplied by +-1 so that its entry of largest magnitude (the
+    first such) is positive: the sign convention that makes singular vectors
+    of a simple singular value unique."""
+    U = np.array(U, dtype=np.float64, copy=True)
+    for r in range(U.shape[0]):
+        k = int(np.argmax(np.abs(U[r])))
+        if U[r, k] < 0:
+            U[r] = -U[r]
+    return U
+
+
+def hosvd_factors(X, J):
+    """Truncated HOSVD (the Tucker factors): for each mode n, the J_n leading
+    eigenvectors of the Gram matrix of the mode-n unfolding (its leading left
+    singular vectors), as the rows of a J_n x I_n factor, by decreasing
+    eigenvalue, sign-fixed; also the eigenvalues (squared singular values) in
+    decreasing order.  The symmetric eigensolver is numpy's (a library step)."""
+    factors, evals = [], []
+    for mode in (1, 2, 3):
+        w, V = np.linalg.eigh(gram(X, mode))
+        order = np.argsort(-w, kind="stable")
+        evals.append(w[order])
+        factors.append(sign_fixed_rows(V[:, order[:J[mode - 1]]].T))
+    return factors, evals

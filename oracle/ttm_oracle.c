@@ -455,3 +455,35 @@ int ttmo_reorder(const int64_t *dims, const int *perm, const void *X, void *Y, i
     }
     return 0;
 }
+
+/* ---------------------------------------------------------------------------
+ * Gram matrix of a mode-n unfolding, G = X_(n) X_(n)^T (I_n x I_n):
+ *   G[a][b] = sum over the other two indices of X[..a..] X[..b..],
+ * the matrix whose leading eigenvectors are the leading left singular
+ * vectors of X_(n), i.e. the truncated HOSVD factor of mode n.  Sequential
+ * sums in ascending order of the other indices (i1 before i2 before i3).
+ * ------------------------------------------------------------------------- */
+int ttmo_gram(const int64_t *dims, int mode, const double *X, double *G)
+{
+    if (mode < 1 || mode > 3) return -1;
+    const int64_t n1 = dims[0], n2 = dims[1], n3 = dims[2];
+    const int64_t n = dims[mode - 1];
+#pragma omp parallel for schedule(static)
+    for (int64_t a = 0; a < n; ++a) {
+        for (int64_t b = 0; b < n; ++b) {
+            double s = 0.0;
+            if (mode == 1) {
+                for (int64_t j = 0; j < n2; ++j)
+                    for (int64_t k = 0; k < n3; ++k) s += X[(a * n2 + j) * n3 + k] * X[(b * n2 + j) * n3 + k];
+            } else if (mode == 2) {
+                for (int64_t i = 0; i < n1; ++i)
+                    for (int64_t k = 0; k < n3; ++k) s += X[(i * n2 + a) * n3 + k] * X[(i * n2 + b) * n3 + k];
+            } else {
+                for (int64_t i = 0; i < n1; ++i)
+                    for (int64_t j = 0; j < n2; ++j) s += X[(i * n2 + j) * n3 + a] * X[(i * n2 + j) * n3 + b];
+            }
+            G[a * n + b] = s;
+        }
+    }
+    return 0;
+}

@@ -422,3 +422,52 @@ def test_reorder_rejects_bad_perm():
     for bad in [(0, 0, 1), (0, 1, 3), (-1, 1, 2)]:
         with pytest.raises(ValueError):
             oracle.reorder(X, bad)
+
+
+# ---------------------------------------------------------------------------
+# Gram matrices of the unfoldings and the truncated HOSVD factors
+# ---------------------------------------------------------------------------
+def unfold(X, mode):
+    return np.moveaxis(np.asarray(X, dtype=np.float64), mode - 1, 0).reshape(X.shape[mode - 1], -1)
+
+
+def test_gram_matches_unfolding_product():
+    rng = np.random.default_rng(71)
+    X = rng.standard_normal((5, 7, 6))
+    for mode in (1, 2, 3):
+        U = unfold(X, mode)
+        np.testing.assert_allclose(oracle.gram(X, mode), U @ U.T, rtol=1e-13, atol=1e-12)
+
+
+def test_hosvd_factors_match_svd_of_the_unfoldings():
+    """Eigenvectors of the Gram matrices (the oracle's route) against the left
+    singular vectors of the unfoldings (numpy's SVD): same subspaces, and the
+    same vectors after the sign convention where singular values are simple."""
+    rng = np.random.default_rng(72)
+    X = rng.standard_normal((6, 8, 7))
+    J = (3, 4, 5)
+    fs, ev = oracle.hosvd_factors(X, J)
+    for mode in (1, 2, 3):
+        Usvd, sv, _ = np.linalg.svd(unfold(X, mode), full_matrices=False)
+        np.testing.assert_allclose(ev[mode - 1][: len(sv)], sv ** 2, rtol=1e-10, atol=1e-10)
+        ref = oracle.sign_fixed_rows(Usvd[:, : J[mode - 1]].T)
+        np.testing.assert_allclose(fs[mode - 1], ref, atol=1e-10)
+        np.testing.assert_allclose(fs[mode - 1] @ fs[mode - 1].T, np.eye(J[mode - 1]), atol=1e-13)
+
+
+def test_hosvd_recovers_a_low_multilinear_rank_tensor():
+    """X = G x1 P x2 Q x3 R with orthonormal-column P, Q, R of ranks (2, 3, 2):
+    the truncated factors span exactly those column spaces, and the chain with
+    the factors and back with their transposes returns X."""
+    rng = np.random.default_rng(73)
+    I, r = (9, 10, 8), (2, 3, 2)
+    core = rng.standard_normal(r)
+    Ps = [np.linalg.qr(rng.standard_normal((I[n], r[n])))[0] for n in range(3)]
+    X = oracle.chain(core, *Ps)
+    fs, ev = oracle.hosvd_factors(X, r)
+    for n in range(3):
+        np.testing.assert_allclose(fs[n].T @ fs[n], Ps[n] @ Ps[n].T, atol=1e-11)
+        assert np.all(np.abs(ev[n][r[n]:]) < 1e-13 * ev[n][0])   # rounding level of the eigensolver
+    G = oracle.chain(X, *fs)
+    back = oracle.chain(G, *(f.T for f in fs))
+    np.testing.assert_allclose(back, X, atol=1e-12)
