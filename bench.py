@@ -21,7 +21,7 @@ Other workloads: --workload c2 (X 512^3 float32, J = 64, float32),
 c4 (20000 ragged cuboids), c5 (X 256^3 float32, J = 32, forward + adjoint),
 c6 (compact sixth-order derivative sweeps along each mode of a 512^3
 float64 field), reorder (moves of a 512^3 float64 field between
-directional layouts).
+directional layouts), hosvd (the FP64 HOSVD factors of a 128^3 tensor).
 """
 from __future__ import annotations
 
@@ -410,12 +410,37 @@ def bench_reorder(args, torch, ttm):
             "per_perm": res}
 
 
+def bench_hosvd(args, torch, ttm):
+    """Truncated HOSVD factors of X 128^3 float64 (ranks 16): three Gram
+    matrices on the FP64 matrix cores and three Jacobi eigensolves."""
+    I, J = 128, 16
+    dev = "cuda:0"
+    g = torch.Generator(device=dev)
+    g.manual_seed(8)
+    X = torch.randn((I, I, I), dtype=torch.float64, device=dev, generator=g)
+    fn = lambda: ttm.hosvd(X, (J, J, J))
+    ms = timed(fn, args.steps, args.warmup, torch)["median"]
+    kt = kernel_times(fn, args.steps, torch, ttm)
+    gram_ms = kt["ttm_gram"][0] * kt["ttm_gram"][1] + (kt["ttm_gram_sum"][0] * kt["ttm_gram_sum"][1]
+                                                       if "ttm_gram_sum" in kt else 0.0)
+    gram_flops = 3 * 2.0 * I * I * I ** 3 / I
+    tf = gram_flops / (gram_ms * 1e-3) / 1e12
+    return {"metric": "HOSVD factors ms (3 modes)", "value": round(ms, 4), "unit": "ms", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": False,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "X 128^3 float64 N(0,1); ranks (16, 16, 16)", "I": I, "J": J},
+            "roofline": {"bound": "mfma", "achieved": round(tf, 2), "peak": 78.6, "unit": "TFLOP/s",
+                         "frac": round(tf / 78.6, 4), "traffic": None, "kernel": "ttm_gram (FP64 Gram matrices)",
+                         "kernel_ms": round(gram_ms, 4)},
+            "kernels_ms": {k: round(v[0] * v[1], 4) for k, v in kt.items()}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c4", "c5", "c6", "copy", "reorder"])
+    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c4", "c5", "c6", "copy", "reorder", "hosvd"])
     ap.add_argument("--forms", default="bf16x3,f32,bf16",
                     help="c3: arithmetic forms to run (bf16x3 is the headline and must be included)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -431,7 +456,7 @@ def main():
         sys.exit(1)
     torch.cuda.init()
     fn = {"c3": bench_dense_precision, "c2": bench_c2, "c4": bench_c4, "c5": bench_c5, "c6": bench_c6, "copy": bench_copy,
-          "reorder": bench_reorder}[args.workload]
+          "reorder": bench_reorder, "hosvd": bench_hosvd}[args.workload]
     line = fn(args, torch, ttm)
     print(json.dumps(line), flush=True)
 

@@ -301,6 +301,29 @@ int ttm_compact_apply(const int64_t *dims, int mode, const void *X, void *Y, int
                       const ttm_compact_coef *coef, void *ws, size_t ws_bytes, int prepared, void *stream);
 
 /*
+ * Truncated HOSVD factors (the Tucker factors the chain applies): for each
+ * mode n, the J[n] leading left singular vectors of the unfolding X_(n), as
+ * the rows of an J[n] x I[n] factor, computed in FP64 on the GPU: the Gram
+ * matrix X_(n) X_(n)^T on the FP64 matrix cores, then its symmetric
+ * eigendecomposition by the cyclic Jacobi method in one workgroup.  Rows come
+ * in decreasing order of their eigenvalue (squared singular value), each
+ * with its entry of largest magnitude positive.  X x1 A x2 B x3 C with these
+ * factors (ttm_chain) is the Tucker core.
+ *   shape  I[n] in [1, 128], J[n] in [1, I[n]]
+ *   X      device, F64, [I1][I2][I3]
+ *   A,B,C  device, F64, [J1][I1], [J2][I2], [J3][I3]
+ *   evals  device, F64, I1 + I2 + I3 values (nullable): every eigenvalue of
+ *          each mode's Gram matrix, decreasing, mode 1 first
+ *   ws     ttm_hosvd_workspace_size(shape) bytes, 16-byte aligned
+ * Where eigenvalues repeat, the corresponding vectors are any orthonormal
+ * basis of their space.  Errors: TTM_ERR_INVALID_ARG, TTM_ERR_UNSUPPORTED
+ * (a mode longer than 128), TTM_ERR_WORKSPACE, TTM_ERR_ALIAS, TTM_ERR_HIP.
+ */
+size_t ttm_hosvd_workspace_size(const ttm_shape *shape);
+int ttm_hosvd(const ttm_shape *shape, const void *X, void *A, void *B, void *C, void *evals, void *ws,
+              size_t ws_bytes, void *stream);
+
+/*
  * A field moved between directional layouts (Sec. 4.1: each direction has
  * its own layout, in which that direction's lines are contiguous, and Sec.
  * 5.3 counts these reorders in the data movement of a transport step):

@@ -5,10 +5,10 @@ The computation lives in libttm.so (hand-written HIP kernels behind the C
 interface in include/ttm.h); this package is its PyTorch binding.
 """
 from .ttm import (COMPACT6, BatchedPlan, TTMChain, chain, chain_backward, chain_backward_workspace_size,
-                  chain_noalloc, chain_workspace_size, compact_apply, reorder, set_slab_kernel, stream_copy,
+                  chain_noalloc, chain_workspace_size, compact_apply, hosvd, reorder, set_slab_kernel, stream_copy,
                   timing_collect, timing_enable, ttm_chain)
 
 __all__ = ["COMPACT6", "BatchedPlan", "TTMChain", "chain", "chain_backward", "chain_backward_workspace_size",
-           "chain_noalloc", "chain_workspace_size", "compact_apply", "reorder", "set_slab_kernel", "stream_copy",
+           "chain_noalloc", "chain_workspace_size", "compact_apply", "hosvd", "reorder", "set_slab_kernel", "stream_copy",
            "timing_collect",
            "timing_enable", "ttm_chain"]

@@ -61,6 +61,8 @@ SIGNATURES = {
     "ttm_batched_plan_config": (INT, [P, P]),
     "ttm_stream_copy": (INT, [P, P, SZ, P]),
     "ttm_reorder": (INT, [P, P, P, P, INT, INT, P]),
+    "ttm_hosvd_workspace_size": (SZ, [PShape]),
+    "ttm_hosvd": (INT, [PShape, P, P, P, P, P, P, SZ, P]),
     "ttm_compact_workspace_size": (SZ, [I64, INT]),
     "ttm_compact_apply": (INT, [P, INT, P, P, INT, ctypes.POINTER(CompactCoef), P, SZ, INT, P]),
     "ttm_timing_enable": (INT, [INT]),

@@ -1,0 +1,281 @@
+// ttm_hosvd.hip -- the truncated HOSVD factors around the chain, in FP64 on
+// the GPU: for each mode n the J_n leading left singular vectors of the
+// unfolding X_(n), as the rows of the factor that the chain then applies
+// (X x1 U1 x2 U2 x3 U3 is the Tucker core).
+//
+// Per mode: the Gram matrix G = X_(n) X_(n)^T (I_n x I_n) on the FP64 matrix
+// cores (the strided GEMM with a split k range and a fixed-order sum of the
+// splits), then its eigendecomposition by the cyclic Jacobi method in one
+// workgroup, G resident in LDS (I_n <= 128): each sweep visits every pair
+// (p, q) once, in rounds of I_n / 2 disjoint pairs (the round-robin
+// schedule), every round one set of plane rotations applied to the rows,
+// then the columns, of G and to the columns of the eigenvector matrix V.
+// Sweeps repeat until the off-diagonal mass is below 1e-30 of the diagonal's
+// (at most 40).  The eigenvalues sorted in decreasing order select the
+// columns of V that become the factor's rows, each with its entry of largest
+// magnitude made positive (the sign convention that makes the vector of a
+// simple eigenvalue unique).
+#include <algorithm>
+#include <cstring>
+
+#include "ttm_device.hpp"
+#include "ttm_gemm.hpp"
+#include "ttm_host.hpp"
+
+namespace ttm {
+
+constexpr int EIG_NMAX = 128;
+constexpr int EIG_THREADS = 1024;
+constexpr int EIG_MAX_SWEEPS = 40;
+
+// V (n x n, column k = eigenvector k) and sorted outputs: rows r < J of U
+// (J x n) and the n eigenvalues in decreasing order (nullable).
+__global__ void __launch_bounds__(EIG_THREADS) k_sym_jacobi(const double *G, int n, double *V, int J, double *U,
+                                                             double *evals) {
+    __shared__ double A[EIG_NMAX * EIG_NMAX];
+    __shared__ double rc[EIG_NMAX / 2 + 1], rs[EIG_NMAX / 2 + 1];
+    __shared__ int rp[EIG_NMAX / 2 + 1], rq[EIG_NMAX / 2 + 1];
+    __shared__ double red[EIG_THREADS / 64][2];
+    __shared__ int order[EIG_NMAX];
+    __shared__ int done;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nn = n * n;
+    for (int e = tid; e < nn; e += EIG_THREADS) {
+        A[e] = G[e];
+        V[e] = (e / n) == (e % n) ? 1.0 : 0.0;
+    }
+    const int m = n + (n & 1);          // players of the round-robin (one idle slot when n is odd)
+    const int np = m / 2;
+    __syncthreads();
+    for (int sweep = 0; sweep < EIG_MAX_SWEEPS; ++sweep) {
+        for (int r = 0; r < m - 1; ++r) {
+            // rotation of every pair of this round
+            if (tid < np) {
+                int p, q;
+                if (tid == 0) { p = r; q = m - 1; }
+                else { p = (r + tid) % (m - 1); q = (r - tid + (m - 1)) % (m - 1); }
+                double c = 1.0, s = 0.0;
+                if (p < n && q < n) {
+                    const double apq = A[p * n + q];
+                    if (apq != 0.0) {
+                        const double tau = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
+                        const double at = fabs(tau);
+                        const double t = at > 1e150 ? 0.5 / tau
+                                                    : (tau >= 0.0 ? 1.0 : -1.0) / (at + sqrt(1.0 + tau * tau));
+                        c = 1.0 / sqrt(1.0 + t * t);
+                        s = t * c;
+                    }
+                }
+                rp[tid] = p;
+                rq[tid] = q;
+                rc[tid] = c;
+                rs[tid] = s;
+            }
+            __syncthreads();
+            // rows p and q of A
+            for (int w = tid; w < np * n; w += EIG_THREADS) {
+                const int k = w / n, j = w - k * n;
+                const int p = rp[k], q = rq[k];
+                if (p < n && q < n) {
+                    const double c = rc[k], s = rs[k];
+                    const double ap = A[p * n + j], aq = A[q * n + j];
+                    A[p * n + j] = c * ap - s * aq;
+                    A[q * n + j] = s * ap + c * aq;
+                }
+            }
+            __syncthreads();
+            // columns p and q of A and of V
+            for (int w = tid; w < np * n; w += EIG_THREADS) {
+                const int k = w / n, i = w - k * n;
+                const int p = rp[k], q = rq[k];
+                if (p < n && q < n) {
+                    const double c = rc[k], s = rs[k];
+                    const double ap = A[i * n + p], aq = A[i * n + q];
+                    A[i * n + p] = c * ap - s * aq;
+                    A[i * n + q] = s * ap + c * aq;
+                    const double vp = V[i * n + p], vq = V[i * n + q];
+                    V[i * n + p] = c * vp - s * vq;
+                    V[i * n + q] = s * vp + c * vq;
+                }
+            }
+            __syncthreads();
+        }
+        // off-diagonal and diagonal mass, fixed-order reduction
+        double off = 0.0, dia = 0.0;
+        for (int e = tid; e < nn; e += EIG_THREADS) {
+            const double v = A[e];
+            if (e / n == e % n) dia += v * v;
+            else off += v * v;
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            off += __shfl_xor(off, o);
+            dia += __shfl_xor(dia, o);
+        }
+        if (lane == 0) { red[wave][0] = off; red[wave][1] = dia; }
+        __syncthreads();
+        if (tid == 0) {
+            double so = 0.0, sd = 0.0;
+            for (int w = 0; w < EIG_THREADS / 64; ++w) { so += red[w][0]; sd += red[w][1]; }
+            done = so <= 1e-30 * sd;
+        }
+        __syncthreads();
+        if (done) break;
+    }
+    // decreasing order of the eigenvalues (ties: lower index first)
+    if (tid < n) {
+        const double li = A[tid * n + tid];
+        int rank = 0;
+        for (int j = 0; j < n; ++j) {
+            const double lj = A[j * n + j];
+            rank += (lj > li || (lj == li && j < tid)) ? 1 : 0;
+        }
+        order[rank] = tid;
+    }
+    __syncthreads();
+    if (evals && tid < n) evals[tid] = A[order[tid] * n + order[tid]];
+    // factor rows: one wave per row, sign fixed by the entry of largest magnitude
+    for (int row = wave; row < J; row += EIG_THREADS / 64) {
+        const int col = order[row];
+        double best = -1.0;
+        int bi = n;
+        for (int i = lane; i < n; i += 64) {
+            const double a = fabs(V[i * n + col]);
+            if (a > best || (a == best && i < bi)) { best = a; bi = i; }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ob = __shfl_xor(best, o);
+            const int oi = __shfl_xor(bi, o);
+            if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+        }
+        const double sgn = V[bi * n + col] < 0.0 ? -1.0 : 1.0;
+        for (int i = lane; i < n; i += 64) U[int64_t(row) * n + i] = sgn * V[i * n + col];
+    }
+}
+
+struct HosvdPlan {
+    int64_t nmax;
+    int ks[3];
+    size_t off_G, off_V, off_P, total;
+};
+
+static void hosvd_plan(const ttm_shape &s, HosvdPlan &p) {
+    p.nmax = std::max(s.I[0], std::max(s.I[1], s.I[2]));
+    const int64_t KT = GemmCfg<M_F64>::KT;
+    int kmax = 1;
+    for (int n = 0; n < 3; ++n) {
+        const int64_t K = s.I[0] * s.I[1] * s.I[2] / s.I[n];
+        const int64_t tiles = ceil_div(s.I[n], 64) * ceil_div(s.I[n], 64);
+        // about 256 workgroups in all, each split at least eight chunks long
+        int64_t k = std::min<int64_t>(ceil_div(256, tiles), ceil_div(K, 8 * KT));
+        k = std::max<int64_t>(1, std::min<int64_t>(k, 64));
+        p.ks[n] = int(k);
+        kmax = std::max(kmax, p.ks[n]);
+    }
+    const size_t nn = size_t(p.nmax * p.nmax) * 8;
+    p.off_G = 0;
+    p.off_V = (nn + 255) & ~size_t(255);
+    p.off_P = p.off_V + ((nn + 255) & ~size_t(255));
+    p.total = p.off_P + (kmax > 1 ? size_t(kmax) * nn : 0);
+}
+
+static int gram_f64(const ttm_shape &s, const double *X, int mode, double *G, double *part, int ks, hipStream_t st) {
+    const int64_t I1 = s.I[0], I2 = s.I[1], I3 = s.I[2];
+    const int64_t n = s.I[mode - 1];
+    GemmArgs a;
+    memset(&a, 0, sizeof a);
+    a.A = X;
+    a.B = X;
+    a.P = 1;
+    a.M = n;
+    a.N = n;
+    if (mode == 1) {
+        a.K = I2 * I3; a.Ki = a.K;
+        a.sam = I2 * I3; a.saki = 1;
+        a.sbn = I2 * I3; a.sbki = 1;
+    } else if (mode == 2) {
+        a.K = I1 * I3; a.Ki = I3;
+        a.sam = I3; a.sako = I2 * I3; a.saki = 1;
+        a.sbn = I3; a.sbko = I2 * I3; a.sbki = 1;
+    } else {
+        a.K = I1 * I2; a.Ki = a.K;
+        a.sam = 1; a.saki = I3;
+        a.sbn = 1; a.sbki = I3;
+    }
+    const int64_t KT = GemmCfg<M_F64>::KT;
+    a.k_per_split = round_up(ceil_div(a.K, ks), KT);
+    const int nsplit = int(ceil_div(a.K, a.k_per_split));
+    a.C = nsplit > 1 ? static_cast<void *>(part) : static_cast<void *>(G);
+    a.scm = n;
+    a.scn = 1;
+    a.scs = n * n;
+    dim3 grid(unsigned(ceil_div(n, 64) * ceil_div(n, 64)), unsigned(nsplit), 1);
+    int rc = launch("ttm_gram", st, [&] { hipLaunchKernelGGL((k_gemm<M_F64, false, false>), grid, dim3(256), 0, st, a); });
+    if (rc || nsplit == 1) return rc;
+    return launch("ttm_gram_sum", st, [&] {
+        hipLaunchKernelGGL(k_sum_splits<double>, dim3(unsigned(ceil_div(n * n, 256))), dim3(256), 0, st, part, n * n,
+                           nsplit, n * n, G);
+    });
+}
+
+static int hosvd_check_shape(const ttm_shape *s) {
+    if (!s) return TTM_ERR_INVALID_ARG;
+    for (int n = 0; n < 3; ++n) {
+        if (s->I[n] < 1 || s->J[n] < 1 || s->J[n] > s->I[n]) return TTM_ERR_INVALID_ARG;
+        if (s->I[n] > EIG_NMAX) return TTM_ERR_UNSUPPORTED;
+    }
+    return TTM_OK;
+}
+
+}  // namespace ttm
+
+using namespace ttm;
+
+extern "C" {
+
+size_t ttm_hosvd_workspace_size(const ttm_shape *shape) {
+    if (hosvd_check_shape(shape) != TTM_OK) return 0;
+    HosvdPlan p;
+    hosvd_plan(*shape, p);
+    return p.total;
+}
+
+int ttm_hosvd(const ttm_shape *shape, const void *X, void *A, void *B, void *C, void *evals, void *ws,
+              size_t ws_bytes, void *stream) {
+    int rc = hosvd_check_shape(shape);
+    if (rc) return rc;
+    if (!X || !A || !B || !C) return TTM_ERR_INVALID_ARG;
+    if (!aligned(X, 8) || !aligned(A, 8) || !aligned(B, 8) || !aligned(C, 8) || (evals && !aligned(evals, 8)))
+        return TTM_ERR_INVALID_ARG;
+    HosvdPlan p;
+    hosvd_plan(*shape, p);
+    if (!ws || ws_bytes < p.total) return TTM_ERR_WORKSPACE;
+    if (!aligned(ws, 16)) return TTM_ERR_INVALID_ARG;
+    const ttm_shape &s = *shape;
+    const size_t nx = size_t(s.I[0] * s.I[1] * s.I[2]) * 8;
+    void *outs[3] = {A, B, C};
+    for (int n = 0; n < 3; ++n) {
+        const size_t nu = size_t(s.J[n] * s.I[n]) * 8;
+        if (overlaps(outs[n], nu, X, nx) || overlaps(outs[n], nu, ws, p.total)) return TTM_ERR_ALIAS;
+        for (int k = 0; k < n; ++k)
+            if (overlaps(outs[n], nu, outs[k], size_t(s.J[k] * s.I[k]) * 8)) return TTM_ERR_ALIAS;
+    }
+    if (overlaps(ws, p.total, X, nx)) return TTM_ERR_ALIAS;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    unsigned char *w = static_cast<unsigned char *>(ws);
+    double *G = reinterpret_cast<double *>(w + p.off_G), *V = reinterpret_cast<double *>(w + p.off_V);
+    double *part = reinterpret_cast<double *>(w + p.off_P);
+    int64_t eoff = 0;
+    for (int n = 0; n < 3; ++n) {
+        if ((rc = gram_f64(s, static_cast<const double *>(X), n + 1, G, part, p.ks[n], st))) return rc;
+        double *ev = evals ? static_cast<double *>(evals) + eoff : nullptr;
+        rc = launch("ttm_sym_jacobi", st, [&] {
+            hipLaunchKernelGGL(k_sym_jacobi, dim3(1), dim3(EIG_THREADS), 0, st, G, int(s.I[n]), V, int(s.J[n]),
+                               static_cast<double *>(outs[n]), ev);
+        });
+        if (rc) return rc;
+        eoff += s.I[n];
+    }
+    return TTM_OK;
+}
+
+}  // extern "C"

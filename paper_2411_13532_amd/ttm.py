@@ -315,3 +315,25 @@ def reorder(X: torch.Tensor, perm, out: torch.Tensor | None = None, accumulate: 
                                  _ptr(out), _DT[X.dtype], int(bool(accumulate)), _stream(X.device))
     check(rc, "ttm_reorder")
     return out
+
+
+def hosvd(X: torch.Tensor, J, with_evals: bool = False):
+    """ttm_hosvd: the truncated HOSVD factors (J_n x I_n, float64) of a float64
+    X, each mode's rows the leading left singular vectors of its unfolding;
+    with_evals also returns each mode's Gram eigenvalues, decreasing."""
+    _need_cuda(X)
+    if X.dim() != 3 or X.dtype != torch.float64:
+        raise ValueError("X must be a 3-way float64 tensor")
+    I = tuple(X.shape)
+    s = _lib.shape(I, J)
+    lib = _lib.load()
+    ws = torch.empty(max(int(lib.ttm_hosvd_workspace_size(ctypes.byref(s))), 1), dtype=torch.uint8,
+                     device=X.device)
+    fs = [torch.empty((int(J[n]), I[n]), dtype=torch.float64, device=X.device) for n in range(3)]
+    ev = torch.empty(sum(I), dtype=torch.float64, device=X.device) if with_evals else None
+    rc = lib.ttm_hosvd(ctypes.byref(s), _ptr(X), *[_ptr(f) for f in fs], _ptr(ev), _ptr(ws), ws.numel(),
+                       _stream(X.device))
+    check(rc, "ttm_hosvd")
+    if not with_evals:
+        return fs
+    return fs, [ev[sum(I[:n]):sum(I[:n + 1])] for n in range(3)]
