@@ -562,11 +562,6 @@ __global__ void __launch_bounds__(SLAB_THREADS, 2) k_slab_dma(const SlabArgs a) 
 
 // s_waitcnt with only the vector-memory count limited (gfx9 encoding:
 // vmcnt bits [3:0] and [15:14], expcnt and lgkmcnt at their maxima).
-template <int N>
-__device__ __forceinline__ void wait_vmcnt() {
-    static_assert(N >= 0 && N < 64, "vmcnt range");
-    __builtin_amdgcn_s_waitcnt((N & 0xf) | ((N >> 4) << 14) | (0x7 << 4) | (0xf << 8));
-}
 
 // Mode-2 step for the bf16 forms with the B loads software-pipelined: W is
 // first converted to its bf16 operand pairs (freeing the accumulators), then
@@ -654,20 +649,6 @@ constexpr int LC_THREADS = 512;
 constexpr int LC_TM = 256;
 constexpr int LC_XSTAGE = LC_TM * 128;               // 32 KiB
 
-__device__ __forceinline__ uint32_t lds_offset(const void *p) {
-    return static_cast<uint32_t>(reinterpret_cast<uintptr_t>((const __attribute__((address_space(3))) char *)p));
-}
-// Direct-to-LDS copy of 16 bytes per lane to LDS byte address m0 + 16 lane,
-// issued through inline assembly so that the compiler does not count it among
-// the vector-memory operations it waits for: its own waits for ordinary loads
-// (which return in order among themselves) then count only those loads
-// instead of falling back to waiting for everything, and the copies are waited
-// for explicitly (wait_vmcnt).  The LDS address is bound to m0 through the
-// operand constraint, so the compiler writes m0 itself and knows it is taken;
-// the s_nop separates that write from the copy that reads it.
-__device__ __forceinline__ void dma16_to_lds_m0(const void *g, uint32_t lds_addr) {
-    asm volatile("s_nop 0\n\tglobal_load_lds_dwordx4 %0, off" : : "v"(g), "{m0}"(lds_addr) : "memory");
-}
 template <int OFF>
 __device__ __forceinline__ u32x4 lds_read16_at(uint32_t addr) {
     static_assert(OFF >= 0 && OFF < 65536 && OFF % 16 == 0, "ds_read_b128 immediate offset");

@@ -157,6 +157,32 @@ __device__ __forceinline__ void dma16_to_lds(const void *g, void *lds_wave_base)
 #endif
 }
 
+__device__ __forceinline__ uint32_t lds_offset(const void *p) {
+    return static_cast<uint32_t>(reinterpret_cast<uintptr_t>((const __attribute__((address_space(3))) char *)p));
+}
+// Direct-to-LDS copy of 16 bytes per lane to LDS byte address m0 + 16 lane,
+// issued through inline assembly so that the compiler does not count it among
+// the vector-memory operations it waits for: its own waits for ordinary loads
+// (which return in order among themselves) then count only those loads
+// instead of falling back to waiting for everything, and the copies are waited
+// for explicitly (wait_vmcnt).  The LDS address is bound to m0 through the
+// operand constraint, so the compiler writes m0 itself and knows it is taken;
+// the s_nop separates that write from the copy that reads it.
+__device__ __forceinline__ void dma16_to_lds_m0(const void *g, uint32_t lds_addr) {
+    asm volatile("s_nop 0\n\tglobal_load_lds_dwordx4 %0, off" : : "v"(g), "{m0}"(lds_addr) : "memory");
+}
+// The same for 4 bytes per lane (LDS byte address m0 + 4 lane).
+__device__ __forceinline__ void dma4_to_lds_m0(const void *g, uint32_t lds_addr) {
+    asm volatile("s_nop 0\n\tglobal_load_lds_dword %0, off" : : "v"(g), "{m0}"(lds_addr) : "memory");
+}
+// wait until at most N vector-memory operations of this wave are outstanding
+// (they complete in issue order)
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 0xf) | ((N >> 4) << 14) | (0x7 << 4) | (0xf << 8));
+}
+
 // LDS accesses of one wavefront are performed in issue order; this only stops
 // the compiler from moving them across a point where the wave's lanes hand
 // data to each other through LDS.

@@ -30,7 +30,14 @@ SHAPES = [((6, 7, 8), (3, 5, 4)), ((37, 70, 65), (20, 9, 33)), ((1, 1, 1), (1, 1
           ((5, 70, 128), (6, 9, 32)), ((3, 33, 192), (4, 5, 12)), ((2, 1, 64), (3, 2, 4)),
           ((300, 7, 320), (2, 3, 20)),
           # ... and J2 <= 32 with I2 a multiple of 64: V and R on streaming kernels too
-          ((5, 64, 128), (6, 9, 32)), ((3, 192, 64), (4, 32, 12))]
+          ((5, 64, 128), (6, 9, 32)), ((3, 192, 64), (4, 32, 12)),
+          # float32 with J <= 32, I3 in {128, 256, 512}, I2 a multiple of 4:
+          # the fused kernels (one, two and eight 16-row blocks per chunk;
+          # ragged last chunks, a single chunk, many slabs, padded J)
+          ((3, 40, 256), (5, 7, 30)), ((2, 100, 512), (32, 32, 32)), ((4, 132, 128), (1, 17, 3)),
+          ((1, 4, 256), (2, 2, 2)), ((7, 256, 256), (32, 32, 32)), ((300, 8, 128), (3, 4, 5))]
+
+FUSED_SHAPES = [((3, 40, 256), (5, 7, 30)), ((2, 100, 512), (32, 32, 32)), ((4, 132, 128), (1, 17, 3))]
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: f"I{s[0]}J{s[1]}")
@@ -61,6 +68,30 @@ def test_partial_gradients_only():
                 assert pins.rel_fro(o.cpu().numpy(), ref[i]) <= 1e-12
             else:
                 assert o is None
+
+
+@pytest.mark.parametrize("shape", FUSED_SHAPES, ids=lambda s: f"I{s[0]}J{s[1]}")
+def test_fused_partial_gradients_and_determinism(shape):
+    """Each gradient alone through the fused float32 kernels, and two runs of
+    all four bit for bit equal (every sum has a fixed order)."""
+    I, J = shape
+    p = workloads.random_problem(I, J, seed=11, dtype=np.float32)
+    G = np.random.default_rng(12).standard_normal(J).astype(np.float32)
+    ins = (G, p["X"], p["A"], p["B"], p["C"])
+    ref = oracle.backward(*ins)
+    args = [dev(t, torch.float32) for t in ins]
+    for k in range(4):
+        need = [i == k for i in range(4)]
+        outs = chain_backward(*args, math="f32", need=need)
+        for i, o in enumerate(outs):
+            if i == k:
+                assert pins.rel_fro(o.double().cpu().numpy(), ref[i]) <= 1e-5, (i, shape)
+            else:
+                assert o is None
+    a = chain_backward(*args, math="f32")
+    b = chain_backward(*args, math="f32")
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
 
 
 def test_adjoint_identity_gpu():
