@@ -321,8 +321,8 @@ def bench_c5(args, torch, ttm):
     ms_f = timed(fwd, args.steps, args.warmup, torch)["median"]
     G = Y - T
     bwd = lambda: ttm.chain_backward(G, X, A, B, C, math="f32")
-    # the step time without per-kernel events (fourteen short launches: the
-    # events' host cost would show in it), then the kernel breakdown
+    # the step time without per-kernel events (their host cost would show in
+    # short launches), then the kernel breakdown
     ms_b = timed(bwd, args.steps, args.warmup, torch)["median"]
     kt_b = {k: n * v for k, (n, v) in kernel_times(bwd, args.steps, torch, ttm).items()}
     fl_f = chain_flops(I, J)

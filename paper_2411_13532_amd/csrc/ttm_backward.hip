@@ -38,11 +38,11 @@ struct BwdPlan {
     bool skinny_vr;   // also J2 <= 32 and I2 a multiple of 64: V and R on streaming kernels
     int dc_splits;
     int64_t dc_rows;
-    // float32 with J <= 32, I3 in {128, 256, 512} and I2 a multiple of 4:
+    // float32 with J <= 32, I3 in {256, 512} and I2 a multiple of 4:
     // the three fused kernels (ncg = I3 / 64), with their own workspace layout
     bool fused;
     int ncg;
-    size_t f_off_H, f_off_V, f_off_B, f_off_C, f_total;
+    size_t f_off_B, f_off_C, f_total;
 };
 
 constexpr int64_t KT_F32 = 32, KT_F64 = 16;
@@ -120,12 +120,10 @@ void make_bwd_plan(const ttm_shape &s, int math, bool dX, bool dA, bool dB, bool
     p.total = off;
 
     p.fused = math == TTM_MATH_F32 && p.J1 <= 32 && p.J2 <= 32 && p.J3 <= 32 &&
-              (p.I3 == 128 || p.I3 == 256 || p.I3 == 512) && p.I2 % 4 == 0 && p.I2 < (int64_t(1) << 24) &&
+              (p.I3 == 256 || p.I3 == 512) && p.I2 % 4 == 0 && p.I2 < (int64_t(1) << 24) &&
               p.I1 < (int64_t(1) << 31);
     p.ncg = int(p.I3 / 64);
     off = 0;
-    p.f_off_H = take(p.fused, p.I1 * 1024);
-    p.f_off_V = take(p.fused, p.I1 * 1024);
     p.f_off_B = take(p.fused, p.I1 * p.J2 * p.I2);
     p.f_off_C = take(p.fused, p.I1 * p.J3 * p.I3);
     p.f_total = off;
@@ -459,40 +457,42 @@ __global__ void __launch_bounds__(256) k_sum_groups_f32(const float *__restrict_
 }
 
 // ---------------------------------------------------------------------------
-// Fused adjoint for float32 with J1, J2, J3 <= 32, I3 in {128, 256, 512} and
-// I2 a multiple of 4: three launches in place of the product sequence above.
+// Fused adjoint for float32 with J1, J2, J3 <= 32, I3 in {256, 512} and I2 a
+// multiple of 4: two launches in place of the product sequence above.
 //
-//   k_bwd_xpass_f32  one workgroup per slab X[i1] reads the slab once and
-//                    contracts it twice on the matrix cores: with C for the
-//                    rows of W = X x3 C, and with R = H x2 B^T (H = G x1 A^T,
-//                    both formed in the workgroup) for the slab's share of dC.
-//                    W never leaves the chip: each chunk of its rows is
-//                    contracted at once with B (the slab's V = X x2 B x3 C,
-//                    for dA) and with H (the slab's share of dB).
-//   k_bwd_dx_f32     dX = R x3 C^T, R formed per 64-row block from H and B.
-//   k_bwd_finish_f32 dB and dC as fixed-order sums of the slabs' shares, and
-//                    dA = G_(1) V_(1)^T.
+//   k_bwd_xpass_f32    one workgroup per slab X[i1] reads the slab once and
+//                      writes dX[i1] once.  With H = G x1 A^T formed in the
+//                      workgroup and R = H x2 B^T formed per chunk of rows,
+//                      each chunk of X is contracted twice on the matrix cores
+//                      (with C for the rows of W = X x3 C, with R for the
+//                      slab's share of dC), and dX = R x3 C^T is written for
+//                      the same rows.  W never leaves the chip: each chunk of
+//                      its rows is contracted with B (the slab's V = X x2 B x3
+//                      C) and with H (the slab's columns of its dB share); at
+//                      the end dA[:, i1] = G_(1) vec(V).
+//   k_bwd_finish_f32   dB and dC as fixed-order sums of the slabs' shares.
 //
 // The slab streams through LDS in chunks of CR rows x I3 (32 KiB): three
 // stages filled by direct-to-LDS copies two chunks ahead, with B's matching
-// CR columns one chunk further ahead (four stages), so that every global read
-// in the loop is a copy the kernel waits for explicitly.  Wave (rh, cq) owns
-// row block rh (16 rows) and column quarter cq (64 columns) of each chunk; it
-// reads its 16 x 64 block twice: in the W product a lane holds row l % 16 and
-// four consecutive columns (the k slots), in the dC product row l / 16 (the k
-// slot) and four consecutive columns (the output column of four products).
-// X words are XOR-swizzled by the row's low four bits so both reads hit 64
-// distinct banks.  Per chunk: products (dC, W partials over cq) | barrier |
-// V, dB and the next chunk's R from the summed W partials | barrier.
-// Padded factor rows and columns (j >= J) are zeros in registers and LDS;
-// rows past I2 read the last row and are masked where they would contribute.
+// CR columns in four stages, so that every global read in the loop is a copy
+// the kernel waits for explicitly.  Wave (rh, cq) owns row block rh (16 rows)
+// and column group cq (64 columns) of each chunk; it reads its 16 x 64 block
+// twice: in the W product a lane holds row l % 16 and four consecutive
+// columns (the k slots), in the dC product row l / 16 of a k step (the k
+// slot) and four consecutive columns (the output columns of four products).
+// X words are XOR-swizzled by the row's low four bits so that both reads
+// cover all banks.  The W partials of the column groups meet in LDS; their
+// V and dB work, and the R of the chunk after next, run in the following
+// iteration ahead of its products (double-buffered W partials and R), so one
+// barrier per chunk orders everything.  Padded factor rows (j >= J) are
+// zeros; rows past I2 read the last row and are masked where they contribute.
 // ---------------------------------------------------------------------------
 constexpr int FB_THREADS = 512;
-constexpr int FB_XSTAGE = 32768;
+constexpr int FB_XSTAGE = 32768;   // bytes of one X chunk
 
 struct FusedArgs {
     const float *X, *A, *B, *C, *G;
-    float *H, *V, *partB, *partC;   // workspace: I1 x 32 x 32, I1 x 32 x 32, I1 x J2 x I2, I1 x J3 x I3
+    float *partB, *partC;           // workspace: I1 x J2 x I2, I1 x J3 x I3
     float *dX, *dA, *dB, *dC;
     int64_t I1;
     int I2, I3, J1, J2, J3;
@@ -508,14 +508,15 @@ __global__ void __launch_bounds__(FB_THREADS, 1) k_bwd_xpass_f32(const FusedArgs
     constexpr int XOPS = FB_XSTAGE / 1024 / 8;   // 16-byte copies per wave per chunk
     constexpr int BSTAGE = 32 * CR * 4;          // bytes of B's chunk: 32 rows j2 x CR columns
     constexpr int BOPS = BSTAGE / 256 / 8;       // 4-byte copies per wave per chunk
-    constexpr int NVP = NRG >= 2 ? NRG / 2 : 1;  // V pieces per wave
-    constexpr int NTK = NRG >= 2 ? NRG / 2 : 1;  // dB / R tiles per wave
-    static_assert(XOPS + BOPS < 16, "vmcnt range");
+    constexpr int WPS = 16 * 33;                 // one wave's W partial tile (padded rows)
+    static_assert(NCG == 4 || NCG == 8, "four or eight 64-column groups");
+    static_assert(XOPS < 16, "vmcnt range");
+    static_assert(32 * FB_THREADS * 4 <= 3 * FB_XSTAGE && 32 * 16 * 4 <= 4 * BSTAGE, "reduction space");
 
     __shared__ __align__(1024) unsigned char xbuf[3 * FB_XSTAGE];
     __shared__ __align__(256) float bbuf[4][32 * CR];
-    __shared__ float rbuf[CR * 32];
-    __shared__ float wpart[NRG][NCG][16 * 33];
+    __shared__ float rbuf[2][CR * 36];          // R rows padded to 36 floats
+    __shared__ float wpart[2][NRG * NCG * WPS];
     __shared__ float hbuf[32 * 33];
 
     const int tid = threadIdx.x, lane = tid & 63;
@@ -526,47 +527,8 @@ __global__ void __launch_bounds__(FB_THREADS, 1) k_bwd_xpass_f32(const FusedArgs
     const int I2 = a.I2, J2 = a.J2, J3 = a.J3;
     const int nch = (I2 + CR - 1) / CR;
     const float *Xs = a.X + i1 * int64_t(I2) * I3C;
-
-    // H[i1] = sum_j1 A[j1][i1] G[j1] (zero-padded to 32 x 32), to LDS and to
-    // the workspace for the dX kernel
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int idx = tid + q * FB_THREADS, j2 = idx >> 5, j3 = idx & 31;
-        float s = 0.f;
-        if (j2 < J2 && j3 < J3) {
-            const float *gp = a.G + j2 * J3 + j3;
-            const int64_t gs = int64_t(J2) * J3;
-#pragma unroll 8
-            for (int j1 = 0; j1 < a.J1; ++j1) s += a.A[int64_t(j1) * a.I1 + i1] * gp[j1 * gs];
-        }
-        hbuf[j2 * 33 + j3] = s;
-        a.H[i1 * 1024 + idx] = s;
-    }
-    // C fragments of the W product: k slot (g, e) of step k is column
-    // 64 cq + 16 k + 4 g + e, output column j = 16 jb + l % 16
-    V16 cf[2][4];
-#pragma unroll
-    for (int jb = 0; jb < 2; ++jb)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int j = 16 * jb + h;
-            cf[jb][k] = ld16(a.C + int64_t(j < J3 ? j : J3 - 1) * I3C + 64 * cq + 16 * k + 4 * g);
-            if (j >= J3) cf[jb][k] = zero16();
-        }
-    wait_vmcnt<0>();
-    __syncthreads();
-    // H fragments: hA[jb][k] = H[16 jb + l%16][4 k + l/16] (dB product),
-    // hB[jb][k] = H[4 k + l/16][16 jb + l%16] (R product)
-    float hA[2][8], hB[2][8];
-#pragma unroll
-    for (int jb = 0; jb < 2; ++jb)
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            hA[jb][k] = hbuf[(16 * jb + h) * 33 + 4 * k + g];
-            hB[jb][k] = hbuf[(4 * k + g) * 33 + 16 * jb + h];
-        }
-
     const uint32_t xlds = lds_offset(xbuf), blds = lds_offset(&bbuf[0][0]);
+
     // chunk c of X into stage c % 3: LDS word q of the stage is row q / WPR,
     // position q % WPR, holding the row's word (q % WPR) ^ (row & 15)
     auto issue_x = [&](int c) __attribute__((always_inline)) {
@@ -591,148 +553,225 @@ __global__ void __launch_bounds__(FB_THREADS, 1) k_bwd_xpass_f32(const FusedArgs
             dma4_to_lds_m0(a.B + int64_t(j2c) * I2 + (col < I2 ? col : I2 - 1), st + uint32_t((wave * BOPS + j) * 256));
         }
     };
-    // before chunk c's work: X(c) and B(c + 1) have landed when at most the
-    // copies issued at the top of iteration c - 1 are outstanding
-    auto wait_chunk = [&](int c) __attribute__((always_inline)) {
-        if (c + 2 < nch) wait_vmcnt<XOPS + BOPS>();
-        else if (c + 1 < nch) wait_vmcnt<XOPS>();
-        else wait_vmcnt<0>();
-    };
-    // tasks after the W partials: V pieces v = wave + 8 i (tile v / NRG, row
-    // block v % NRG); dB tiles t < 2 NRG and R tiles t - 2 NRG for t = t0 + 8 i
-    const int t0 = NRG == 1 ? (wave + 4) & 7 : wave;
 
-    // R of chunk cn (rows masked past I2) into rbuf
-    auto r_tiles = [&](int cn) __attribute__((always_inline)) {
-        const float *bn = bbuf[cn & 3];
+    // copies of the first chunks, then H[i1] = sum_j1 A[j1][i1] G[j1]
+    // (zero-padded to 32 x 32, to LDS and to the workspace for the dX kernel;
+    // rows j1 >= J1 read row J1 - 1 with weight zero, so every load is issued
+    // before the sums) and the C fragments of the W product
+    issue_b(0);
+    if (nch > 1) issue_b(1);
+    issue_x(0);
+    if (nch > 1) issue_x(1);
+    {
+        const int j3 = tid & 31, j2a = tid >> 5, j2b = j2a + 16;
+        const bool va = j2a < J2 && j3 < J3, vb = j2b < J2 && j3 < J3;
+        const int64_t gs = int64_t(J2) * J3;
+        const float *ga = a.G + (va ? j2a * J3 + j3 : 0), *gb = a.G + (vb ? j2b * J3 + j3 : 0);
+        float s0 = 0.f, s1 = 0.f;
 #pragma unroll
-        for (int i = 0; i < NTK; ++i) {
-            const int t = t0 + 8 * i - 2 * NRG;
-            if (t < 0 || t >= 2 * NRG) continue;
-            const int rb = t >> 1, jb3 = t & 1;
-            f32x4 acc = zero_accv<f32x4>();
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const int j2 = 4 * k + g, rho = 16 * rb + h;
-                acc = mfma_f32(bn[j2 * CR + (rho ^ bsw(j2))], hB[jb3][k], acc);
-            }
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int rho = 16 * rb + 4 * g + r;
-                rbuf[rho * 32 + 16 * jb3 + h] = cn * CR + rho < I2 ? acc[r] : 0.f;
-            }
+        for (int j1 = 0; j1 < 32; ++j1) {
+            const int j1c = j1 < a.J1 ? j1 : a.J1 - 1;
+            const float w = j1 < a.J1 ? a.A[int64_t(j1c) * a.I1 + i1] : 0.f;
+            s0 += w * ga[j1c * gs];
+            s1 += w * gb[j1c * gs];
         }
-    };
+        s0 = va ? s0 : 0.f;
+        s1 = vb ? s1 : 0.f;
+        hbuf[j2a * 33 + j3] = s0;
+        hbuf[j2b * 33 + j3] = s1;
+    }
+    // k slot (l/16, e) of step k is column 64 cq + 16 k + 4 (l/16) + e,
+    // output column j3 = 16 jb + l % 16
+    V16 cf[2][4];
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int j = 16 * jb + h;
+            cf[jb][k] = ld16(a.C + int64_t(j < J3 ? j : J3 - 1) * I3C + 64 * cq + 16 * k + 4 * g);
+            if (j >= J3) cf[jb][k] = zero16();
+        }
+    // dX product: k slot (l/16, e) of half hh is j3 = 16 hh + 4 (l/16) + e,
+    // column n of product t is i3 = 64 cq + 4 n + t
+    V16 cfx[2][4];
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int j = 16 * hh + 4 * g + e;
+            cfx[hh][e] = ld16(a.C + int64_t(j < J3 ? j : J3 - 1) * I3C + 64 * cq + 4 * h);
+            if (j >= J3) cfx[hh][e] = zero16();
+        }
+    wait_vmcnt<0>();
+    __syncthreads();
 
-    f32x4 dcacc[2][4], vacc[NVP], dbt[NTK];
+    // Each wave's share of the work on a chunk's W partials: V piece v =
+    // wave (tile v / NRG, row block v % NRG) when v < 4 NRG, and task t:
+    // dB tile t (columns 16 (t / NRG).., row block t % NRG) for t < 2 NRG, R
+    // tile t - 2 NRG (row block (t - 2 NRG) / 2, columns 16 ((t - 2 NRG) & 1)..)
+    // for t < 4 NRG.  Its H operand: hs[k] = H[16 jb2 + l%16][4 k + l/16] for
+    // a dB tile, H[4 k + l/16][16 jb3 + l%16] for an R tile.
+    const int task = NRG == 1 ? (wave + 4) & 7 : wave;
+    const bool has_v = wave < 4 * NRG, is_db = task < 2 * NRG, is_r = !is_db && task < 4 * NRG;
+    const int v_t = wave / NRG, v_rb = wave % NRG;
+    const int db_jb2 = task / NRG, db_rb = task % NRG;
+    const int r_rb = (task - 2 * NRG) >> 1, r_jb3 = (task - 2 * NRG) & 1;
+    float hs[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        hs[k] = is_db ? hbuf[(16 * db_jb2 + h) * 33 + 4 * k + g]
+                      : (is_r ? hbuf[(4 * k + g) * 33 + 16 * r_jb3 + h] : 0.f);
+
+    f32x4 dcacc[2][4], vacc = zero_accv<f32x4>(), dbt = zero_accv<f32x4>(), dxa[4];
 #pragma unroll
     for (int jb = 0; jb < 2; ++jb)
 #pragma unroll
         for (int e = 0; e < 4; ++e) dcacc[jb][e] = zero_accv<f32x4>();
+    float *pb = a.partB + i1 * int64_t(J2) * I2;
+
+    // R of chunk cn (rows past I2 zero) into rbuf[cn & 1]
+    auto r_tiles = [&](int cn) __attribute__((always_inline)) {
+        if (!is_r) return;
+        const float *bn = bbuf[cn & 3];
+        f32x4 acc = zero_accv<f32x4>();
 #pragma unroll
-    for (int i = 0; i < NVP; ++i) vacc[i] = zero_accv<f32x4>();
+        for (int k = 0; k < 8; ++k) {
+            const int j2 = 4 * k + g, rho = 16 * r_rb + h;
+            acc = mfma_f32(bn[j2 * CR + (rho ^ bsw(j2))], hs[k], acc);
+        }
 #pragma unroll
-    for (int i = 0; i < NTK; ++i) dbt[i] = zero_accv<f32x4>();
-    auto store_db = [&](int c) __attribute__((always_inline)) {
-        float *pb = a.partB + i1 * int64_t(J2) * I2;
-#pragma unroll
-        for (int i = 0; i < NTK; ++i) {
-            const int t = t0 + 8 * i;
-            if (t >= 2 * NRG) continue;
-            const int jb2 = t / NRG, rb = t % NRG, col = c * CR + 16 * rb + h;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int j2 = 16 * jb2 + 4 * g + r;
-                if (j2 < J2 && col < I2) pb[int64_t(j2) * I2 + col] = dbt[i][r];
-            }
+        for (int r = 0; r < 4; ++r) {
+            const int rho = 16 * r_rb + 4 * g + r;
+            rbuf[cn & 1][rho * 36 + 16 * r_jb3 + h] = cn * CR + rho < I2 ? acc[r] : 0.f;
         }
     };
-
-    issue_x(0);
-    issue_b(0);
-    if (nch > 1) issue_b(1);
-    if (nch > 1) issue_x(1);
-    if (nch > 2) issue_b(2);
-    wait_chunk(0);
-    __syncthreads();
-    r_tiles(0);
-
-    for (int c = 0; c < nch; ++c) {
-        wait_chunk(c);
-        __syncthreads();
-        if (c > 0) store_db(c - 1);
-        if (c + 2 < nch) issue_x(c + 2);
-        if (c + 3 < nch) issue_b(c + 3);
-
-        // products on this wave's 16 x 64 block of the chunk
-        const float *xs = reinterpret_cast<const float *>(xbuf + (c % 3) * FB_XSTAGE);
-        f32x4 wacc[2] = {zero_accv<f32x4>(), zero_accv<f32x4>()};
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            // dC: k slot = row 16 rh + 4 k + l/16, product e takes column 64 cq + 4 (l%16) + e
-            const int rr = 16 * rh + 4 * k + g;
-            V16 xv;
-            xv.u = *reinterpret_cast<const u32x4 *>(xs + rr * I3C + 4 * ((16 * cq + h) ^ (4 * k + g)));
-            const float r0 = rbuf[rr * 32 + h], r1 = rbuf[rr * 32 + 16 + h];
-            // W: row 16 rh + l%16, k slot (l/16, e) = column 64 cq + 16 k + 4 (l/16) + e
-            const int rw = 16 * rh + h;
-            V16 xw;
-            xw.u = *reinterpret_cast<const u32x4 *>(xs + rw * I3C + 4 * ((16 * cq + 4 * k + g) ^ h));
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                dcacc[0][e] = mfma_f32(r0, xv.f[e], dcacc[0][e]);
-                dcacc[1][e] = mfma_f32(r1, xv.f[e], dcacc[1][e]);
-                wacc[0] = mfma_f32(xw.f[e], cf[0][k].f[e], wacc[0]);
-                wacc[1] = mfma_f32(xw.f[e], cf[1][k].f[e], wacc[1]);
-            }
-        }
-        float *wp = wpart[rh][cq];
-#pragma unroll
-        for (int jb = 0; jb < 2; ++jb)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) wp[(4 * g + r) * 33 + 16 * jb + h] = wacc[jb][r];
-        __syncthreads();
-
-        // V pieces: V[j2][j3] += sum_rows B[j2][row] W[row][j3]
-        const float *bs = bbuf[c & 3];
-#pragma unroll
-        for (int i = 0; i < NVP; ++i) {
-            const int v = wave + 8 * i;
-            if (v >= 4 * NRG) continue;
-            const int t = v / NRG, rb = v % NRG, jb2 = t >> 1, jb3 = t & 1;
+    // V and dB of chunk cp from its summed W partials
+    auto w_work = [&](int cp) __attribute__((always_inline)) {
+        const float *bs = bbuf[cp & 3];
+        const float *wp = wpart[cp & 1];
+        if (has_v) {
+            const int jb2 = v_t >> 1, jb3 = v_t & 1;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const int rho = 16 * rb + 4 * k + g, j2 = 16 * jb2 + h;
+                // V[j2][j3] += sum_rows B[j2][row] W[row][j3]
+                const int rho = 16 * v_rb + 4 * k + g, j2 = 16 * jb2 + h;
                 float av = bs[j2 * CR + (rho ^ bsw(j2))];
-                if (c * CR + rho >= I2) av = 0.f;
+                if (cp * CR + rho >= I2) av = 0.f;
                 float bv = 0.f;
 #pragma unroll
-                for (int q = 0; q < NCG; ++q) bv += wpart[rb][q][(4 * k + g) * 33 + 16 * jb3 + h];
-                vacc[i] = mfma_f32(av, bv, vacc[i]);
+                for (int q = 0; q < NCG; ++q) bv += wp[(v_rb * NCG + q) * WPS + (4 * k + g) * 33 + 16 * jb3 + h];
+                vacc = mfma_f32(av, bv, vacc);
             }
         }
-        // dB tiles of this chunk: dB[j2][row] = sum_j3 H[j2][j3] W[row][j3]
-#pragma unroll
-        for (int i = 0; i < NTK; ++i) {
-            const int t = t0 + 8 * i;
-            if (t >= 2 * NRG) continue;
-            const int jb2 = t / NRG, rb = t % NRG;
+        if (is_db) {
+            // dB[j2][row] = sum_j3 H[j2][j3] W[row][j3]
             f32x4 acc = zero_accv<f32x4>();
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 float bv = 0.f;
 #pragma unroll
-                for (int q = 0; q < NCG; ++q) bv += wpart[rb][q][h * 33 + 4 * k + g];
-                acc = mfma_f32(hA[jb2][k], bv, acc);
+                for (int q = 0; q < NCG; ++q) bv += wp[(db_rb * NCG + q) * WPS + h * 33 + 4 * k + g];
+                acc = mfma_f32(hs[k], bv, acc);
             }
-            dbt[i] = acc;
+            dbt = acc;
         }
+    };
+    // stores of results kept in registers: a chunk's dB tile and dX block
+    auto store_db = [&](int cp) __attribute__((always_inline)) {
+        if (!is_db) return;
+        const int col = cp * CR + 16 * db_rb + h;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j2 = 16 * db_jb2 + 4 * g + r;
+            if (j2 < J2 && col < I2) pb[int64_t(j2) * I2 + col] = dbt[r];
+        }
+    };
+    float *dXs = a.dX ? a.dX + i1 * int64_t(I2) * I3C + 64 * cq + 4 * h : nullptr;
+    auto store_dx = [&](int cp) __attribute__((always_inline)) {
+        if (!dXs) return;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = cp * CR + 16 * rh + 4 * g + r;
+            const f32x4 v = {dxa[0][r], dxa[1][r], dxa[2][r], dxa[3][r]};
+            if (row < I2) __builtin_nontemporal_store(v, reinterpret_cast<f32x4 *>(dXs + int64_t(row) * I3C));
+        }
+    };
+
+    r_tiles(0);
+    for (int c = 0; c < nch; ++c) {
+        // X(c) and B(c + 1) have landed when at most the X copies issued in
+        // iteration c - 1 (the last copies, after its B copies) are
+        // outstanding; stores issued after them only make the wait longer
+        if (c + 1 < nch) wait_vmcnt<XOPS>();
+        else wait_vmcnt<0>();
+        __syncthreads();
+        // the previous iterations' results go out ahead of this iteration's
+        // copies, so that the next wait finds them older than the copies
+        if (c > 0) store_dx(c - 1);
+        if (c > 1) store_db(c - 2);
+        if (c + 2 < nch) {
+            issue_b(c + 2);
+            issue_x(c + 2);
+        }
+        // the previous chunk's W work and the next chunk's R run ahead of
+        // this chunk's products (different buffers; the barrier above orders
+        // them against both)
+        if (c > 0) w_work(c - 1);
         if (c + 1 < nch) r_tiles(c + 1);
+
+        // products on this wave's 16 x 64 block of the chunk
+        const float *xs = reinterpret_cast<const float *>(xbuf + (c % 3) * FB_XSTAGE);
+        const float *rs = rbuf[c & 1];
+        f32x4 wacc[2][2];
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb) wacc[jb][0] = wacc[jb][1] = zero_accv<f32x4>();
+        // dC: k slot = row 16 rh + 4 k + l/16, product e takes column 64 cq + 4 (l%16) + e;
+        // W: row 16 rh + l%16, k slot (l/16, e) = column 64 cq + 16 k + 4 (l/16) + e
+        const float *xrow_c = xs + (16 * rh + g) * I3C + 64 * cq;
+        const float *xrow_w = xs + (16 * rh + h) * I3C + 64 * cq + 4 * (g ^ (h & 3));
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            V16 xv, xw;
+            xv.u = *reinterpret_cast<const u32x4 *>(xrow_c + 4 * k * I3C + 4 * (h ^ (4 * k + g)));
+            xw.u = *reinterpret_cast<const u32x4 *>(xrow_w + 16 * (k ^ (h >> 2)));
+            const int rr = 16 * rh + 4 * k + g;
+            const float r0 = rs[rr * 36 + h], r1 = rs[rr * 36 + 16 + h];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                dcacc[0][e] = mfma_f32(r0, xv.f[e], dcacc[0][e]);
+                dcacc[1][e] = mfma_f32(r1, xv.f[e], dcacc[1][e]);
+                wacc[0][k & 1] = mfma_f32(xw.f[e], cf[0][k].f[e], wacc[0][k & 1]);
+                wacc[1][k & 1] = mfma_f32(xw.f[e], cf[1][k].f[e], wacc[1][k & 1]);
+            }
+        }
+        float *wp = wpart[c & 1] + (rh * NCG + cq) * WPS;
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) wp[(4 * g + r) * 33 + 16 * jb + h] = wacc[jb][0][r] + wacc[jb][1][r];
+        // dX[row][i3] = sum_j3 R[row][j3] C[j3][i3] for this wave's block
+        if (dXs) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) dxa[t] = zero_accv<f32x4>();
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) {
+                V16 ra;
+                ra.u = *reinterpret_cast<const u32x4 *>(rs + (16 * rh + h) * 36 + 16 * hh + 4 * g);
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) dxa[t] = mfma_f32(ra.f[e], cfx[hh][e].f[t], dxa[t]);
+            }
+        }
     }
+    store_dx(nch - 1);
+    if (nch > 1) store_db(nch - 2);
+    __syncthreads();
+    w_work(nch - 1);
     store_db(nch - 1);
 
     // the row blocks' dC shares and the V pieces are added through LDS in a
-    // fixed order (all copies have been consumed: the X stages are free)
+    // fixed order (no copy is outstanding: the stages are free)
     __syncthreads();
     float *red = reinterpret_cast<float *>(xbuf);
     float *vred = red + (NRG - 1) * NCG * 2048;
@@ -745,13 +784,9 @@ __global__ void __launch_bounds__(FB_THREADS, 1) k_bwd_xpass_f32(const FusedArgs
                 for (int r = 0; r < 4; ++r)
                     red[((rh - 1) * NCG + cq) * 2048 + ((jb * 4 + e) * 4 + r) * 64 + lane] = dcacc[jb][e][r];
     }
+    if (has_v)
 #pragma unroll
-    for (int i = 0; i < NVP; ++i) {
-        const int v = wave + 8 * i;
-        if (v >= 4 * NRG) continue;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) vred[(v * 4 + r) * 64 + lane] = vacc[i][r];
-    }
+        for (int r = 0; r < 4; ++r) vred[(wave * 4 + r) * 64 + lane] = vacc[r];
     __syncthreads();
     if (rh == 0) {
         for (int q = 1; q < NRG; ++q)
@@ -773,142 +808,90 @@ __global__ void __launch_bounds__(FB_THREADS, 1) k_bwd_xpass_f32(const FusedArgs
                 *reinterpret_cast<f32x4 *>(pc + int64_t(j3) * I3C + 64 * cq + 4 * h) = v;
             }
     }
+    if (!a.dA) return;
+    // V[i1] (32 x 32, padded) into hbuf
     if (wave < 4) {
         const int jb2 = wave >> 1, jb3 = wave & 1;
-        f32x4 s = zero_accv<f32x4>();
-        for (int rb = 0; rb < NRG; ++rb)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) s[r] += vred[((wave * NRG + rb) * 4 + r) * 64 + lane];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) a.V[i1 * 1024 + (16 * jb2 + 4 * g + r) * 32 + 16 * jb3 + h] = s[r];
-    }
-}
-
-// dX[i1][row][i3] = sum_j3 R[row][j3] C[j3][i3] for one 64-row block of slab
-// i1 (grid (I1, ceil(I2 / 64))); R = B^T H[i1] for the block is formed first
-// (eight 16 x 16 tiles, two per wave) and shared through LDS.  Output tile
-// (row block, 64-column group): k slot (l/16, e) of half hh is j3 = 16 hh +
-// 4 (l/16) + e, column n of product t is i3 = 64 cg + 4 n + t, so each lane
-// stores 16 contiguous bytes per row.
-template <int NCG>
-__global__ void __launch_bounds__(256) k_bwd_dx_fused_f32(const FusedArgs a) {
-    constexpr int I3C = 64 * NCG;
-    __shared__ __align__(16) float rt[64 * 36];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, h = lane & 15, g = lane >> 4;
-    const int64_t i1 = blockIdx.x;
-    const int I2 = a.I2, J2 = a.J2, J3 = a.J3;
-    const int row0 = blockIdx.y * 64;
-    const float *Hp = a.H + i1 * 1024;
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int t = wave * 2 + q, rb = t >> 1, jb3 = t & 1;
-        const int row = row0 + 16 * rb + h < I2 ? row0 + 16 * rb + h : I2 - 1;
-        f32x4 acc = zero_accv<f32x4>();
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int j2 = 4 * k + g;
-            acc = mfma_f32(a.B[int64_t(j2 < J2 ? j2 : J2 - 1) * I2 + row], Hp[j2 * 32 + 16 * jb3 + h], acc);
+        for (int r = 0; r < 4; ++r) {
+            float s = 0.f;
+            for (int rb = 0; rb < NRG; ++rb) s += vred[((wave * NRG + rb) * 4 + r) * 64 + lane];
+            hbuf[(16 * jb2 + 4 * g + r) * 33 + 16 * jb3 + h] = s;
         }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) rt[(16 * rb + 4 * g + r) * 36 + 16 * jb3 + h] = acc[r];
     }
     __syncthreads();
-    constexpr int CG_PER = NCG >= 4 ? NCG / 4 : 1;
-    float *dXs = a.dX + (i1 * I2) * int64_t(I3C);
+    // dA[j1][i1] = sum_n G[j1][n] V[i1][n], n = j2 J3 + j3: thread t takes
+    // n = t and t + 512 (coalesced rows of G) for every j1; the 512 partial
+    // sums of each j1 are then added in thread order, sixteen runs of 32 and
+    // then the sixteen run sums
+    {
+        const int NN = J2 * J3;
+        float vv[2];
+        int nn[2];
 #pragma unroll
-    for (int ci = 0; ci < CG_PER; ++ci) {
-        const int cg = NCG >= 4 ? wave + 4 * ci : (wave & 1);
-        V16 cfr[2][4];
-#pragma unroll
-        for (int hh = 0; hh < 2; ++hh)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int j = 16 * hh + 4 * g + e;
-                cfr[hh][e] = ld16(a.C + int64_t(j < J3 ? j : J3 - 1) * I3C + 64 * cg + 4 * h);
-                if (j >= J3) cfr[hh][e] = zero16();
-            }
-        const int rb_lo = NCG >= 4 ? 0 : 2 * (wave >> 1), rb_n = NCG >= 4 ? 4 : 2;
-        for (int rbi = 0; rbi < rb_n; ++rbi) {
-            const int rb = rb_lo + rbi;
-            if (row0 + 16 * rb >= I2) break;
-            V16 ra[2];
-#pragma unroll
-            for (int hh = 0; hh < 2; ++hh) ra[hh].u = *reinterpret_cast<const u32x4 *>(&rt[(16 * rb + h) * 36 + 16 * hh + 4 * g]);
-            f32x4 acc[4];
-#pragma unroll
-            for (int t = 0; t < 4; ++t) acc[t] = zero_accv<f32x4>();
-#pragma unroll
-            for (int hh = 0; hh < 2; ++hh)
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) acc[t] = mfma_f32(ra[hh].f[e], cfr[hh][e].f[t], acc[t]);
-#pragma unroll
-            for (int rr = 0; rr < 4; ++rr) {
-                const int row = row0 + 16 * rb + 4 * g + rr;
-                if (row >= I2) continue;
-                const f32x4 v = {acc[0][rr], acc[1][rr], acc[2][rr], acc[3][rr]};
-                __builtin_nontemporal_store(v, reinterpret_cast<f32x4 *>(dXs + int64_t(row) * I3C + 64 * cg + 4 * h));
-            }
+        for (int m = 0; m < 2; ++m) {
+            const int n = tid + FB_THREADS * m;
+            const bool ok = n < NN;
+            nn[m] = ok ? n : 0;
+            vv[m] = ok ? hbuf[(n / J3) * 33 + n % J3] : 0.f;
         }
-    }
-}
-
-// Blocks [0, nbB) and [nbB, nbB + nbC): 128 consecutive elements of dB (or
-// dC) each, the sum over i1 of the slabs' shares: 32 groups of consecutive
-// i1, each summed in increasing i1 by one thread per 4 elements, then the 32
-// group sums in increasing group order.  Remaining blocks: dA for 4 slabs,
-// dA[j1][i1] = sum_{j2} sum_{j3} G[j1][j2][j3] V[i1][j2][j3], the inner sum
-// by one thread per (j1, j2) in increasing j3, then over j2 in order.
-__global__ void __launch_bounds__(1024) k_bwd_finish_f32(const FusedArgs a) {
-    __shared__ __align__(16) float sm[4 * 1024 + 4 * 32 * 33];
-    const int tid = threadIdx.x;
-    const int b = blockIdx.x;
-    if (b < a.nbB + a.nbC) {
-        const bool isB = b < a.nbB;
-        const int64_t n = isB ? int64_t(a.J2) * a.I2 : int64_t(a.J3) * a.I3;
-        const float *part = isB ? a.partB : a.partC;
-        float *out = isB ? a.dB : a.dC;
-        const int64_t e4 = (int64_t(isB ? b : b - a.nbB) * 32 + (tid & 31)) * 4;
-        const int grp = tid >> 5;
-        const int64_t gs = (a.I1 + 31) / 32, lo = grp * gs, hi = lo + gs < a.I1 ? lo + gs : a.I1;
-        f32x4 s = zero_accv<f32x4>();
-        if (e4 < n)
-            for (int64_t i = lo; i < hi; ++i) s += *reinterpret_cast<const f32x4 *>(part + i * n + e4);
-        f32x4 *red = reinterpret_cast<f32x4 *>(sm);
-        red[grp * 32 + (tid & 31)] = s;
+        float *red2 = reinterpret_cast<float *>(xbuf);   // [32 j1][512 threads], after the dC shares were read
+        float *red3 = &bbuf[0][0];                      // [32 j1][16 runs]
+#pragma unroll
+        for (int j1 = 0; j1 < 32; ++j1) {
+            const float *gr = a.G + int64_t(j1 < a.J1 ? j1 : a.J1 - 1) * NN;
+            red2[j1 * FB_THREADS + tid] = gr[nn[0]] * vv[0] + gr[nn[1]] * vv[1];
+        }
         __syncthreads();
-        if (tid < 32 && e4 < n) {
-            f32x4 t = zero_accv<f32x4>();
-            for (int q = 0; q < 32; ++q) t += red[q * 32 + tid];
-            *reinterpret_cast<f32x4 *>(out + e4) = t;
+        {
+            const int j1 = tid >> 4, run = tid & 15;
+            float s = 0.f;
+            for (int q = 0; q < 32; ++q) s += red2[j1 * FB_THREADS + run * 32 + q];
+            red3[j1 * 16 + run] = s;
         }
-        return;
-    }
-    const int64_t ib = int64_t(b - a.nbB - a.nbC) * 4;
-    float *Vs = sm, *red = sm + 4 * 1024;
-    for (int q = tid; q < 4 * 1024; q += 1024) Vs[q] = ib + q / 1024 < a.I1 ? a.V[ib * 1024 + q] : 0.f;
-    __syncthreads();
-    const int j1 = tid >> 5, j2 = tid & 31;
-    float s[4] = {0.f, 0.f, 0.f, 0.f};
-    if (j1 < a.J1 && j2 < a.J2) {
-        const float *gp = a.G + (int64_t(j1) * a.J2 + j2) * a.J3;
-        for (int j3 = 0; j3 < a.J3; ++j3) {
-            const float gv = gp[j3];
+        __syncthreads();
+        if (tid < a.J1) {
+            float s = 0.f;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) s[i] += gv * Vs[i * 1024 + j2 * 32 + j3];
+            for (int q = 0; q < 16; ++q) s += red3[tid * 16 + q];
+            a.dA[int64_t(tid) * a.I1 + i1] = s;
         }
     }
+}
+
+// Blocks [0, nbB) and [nbB, nbB + nbC): 64 consecutive elements of dB (or
+// dC) each, the sum over i1 of the slabs' shares: 16 groups of consecutive
+// i1, each summed in increasing i1 by one thread per 4 elements, then the 16
+// group sums in increasing group order.
+__global__ void __launch_bounds__(256) k_bwd_finish_f32(const FusedArgs a) {
+    __shared__ f32x4 red[16][16];
+    const int tid = threadIdx.x, b = blockIdx.x;
+    const bool isB = b < a.nbB;
+    const int64_t n = isB ? int64_t(a.J2) * a.I2 : int64_t(a.J3) * a.I3;
+    const float *part = isB ? a.partB : a.partC;
+    float *out = isB ? a.dB : a.dC;
+    const int f = tid & 15, grp = tid >> 4;
+    const int64_t e4 = (int64_t(isB ? b : b - a.nbB) * 16 + f) * 4;
+    const int64_t gs = (a.I1 + 15) / 16, lo = grp * gs, hi = lo + gs < a.I1 ? lo + gs : a.I1;
+    f32x4 s = zero_accv<f32x4>();
+    if (e4 < n)
+        for (int64_t i0 = lo; i0 < hi; i0 += 16) {
+            // sixteen loads in flight, added in increasing i1
+            f32x4 v[16];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) red[(i * 32 + j1) * 33 + j2] = s[i];
-    __syncthreads();
-    if (tid < 128) {
-        const int i = tid >> 5, jj = tid & 31;
-        if (jj < a.J1 && ib + i < a.I1) {
-            float t = 0.f;
-            for (int q = 0; q < 32; ++q) t += red[(i * 32 + jj) * 33 + q];
-            a.dA[int64_t(jj) * a.I1 + ib + i] = t;
+            for (int u = 0; u < 16; ++u)
+                v[u] = *reinterpret_cast<const f32x4 *>(part + (i0 + u < hi ? i0 + u : lo) * n + e4);
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+                if (i0 + u < hi) s += v[u];
         }
+    red[grp][f] = s;
+    __syncthreads();
+    if (tid < 16 && e4 < n) {
+        f32x4 t = zero_accv<f32x4>();
+#pragma unroll
+        for (int q = 0; q < 16; ++q) t += red[q][tid];
+        *reinterpret_cast<f32x4 *>(out + e4) = t;
     }
 }
 
@@ -975,23 +958,13 @@ int run_gemm(GemmArgs a, int64_t batch, bool split, void *part, hipStream_t st, 
 }
 
 template <int NCG>
-int run_fused_ncg(const FusedArgs &fa, bool want_dx, bool want_fin, hipStream_t st) {
-    // static LDS only (at most 160384 bytes, for NCG = 2)
+int run_fused_ncg(const FusedArgs &fa, hipStream_t st) {
     int rc = launch("ttm_bwd_xpass", st, [&] {
         hipLaunchKernelGGL(k_bwd_xpass_f32<NCG>, dim3(unsigned(fa.I1)), dim3(FB_THREADS), 0, st, fa);
     });
-    if (rc) return rc;
-    if (want_dx) {
-        rc = launch("ttm_bwd_dX", st, [&] {
-            hipLaunchKernelGGL(k_bwd_dx_fused_f32<NCG>, dim3(unsigned(fa.I1), unsigned(ceil_div(fa.I2, 64))), dim3(256),
-                               0, st, fa);
-        });
-        if (rc) return rc;
-    }
-    if (!want_fin) return TTM_OK;
-    const int64_t nbA = fa.dA ? ceil_div(fa.I1, 4) : 0;
+    if (rc || fa.nbB + fa.nbC == 0) return rc;
     return launch("ttm_bwd_finish", st, [&] {
-        hipLaunchKernelGGL(k_bwd_finish_f32, dim3(unsigned(fa.nbB + fa.nbC + nbA)), dim3(1024), 0, st, fa);
+        hipLaunchKernelGGL(k_bwd_finish_f32, dim3(unsigned(fa.nbB + fa.nbC)), dim3(256), 0, st, fa);
     });
 }
 
@@ -1004,8 +977,6 @@ int run_fused(const BwdPlan &p, const void *G, const void *X, const void *A, con
     fa.B = static_cast<const float *>(B);
     fa.C = static_cast<const float *>(C);
     fa.G = static_cast<const float *>(G);
-    fa.H = reinterpret_cast<float *>(ws + p.f_off_H);
-    fa.V = reinterpret_cast<float *>(ws + p.f_off_V);
     fa.partB = reinterpret_cast<float *>(ws + p.f_off_B);
     fa.partC = reinterpret_cast<float *>(ws + p.f_off_C);
     fa.dX = static_cast<float *>(dX);
@@ -1015,13 +986,11 @@ int run_fused(const BwdPlan &p, const void *G, const void *X, const void *A, con
     fa.I1 = p.I1;
     fa.I2 = int(p.I2); fa.I3 = int(p.I3);
     fa.J1 = int(p.J1); fa.J2 = int(p.J2); fa.J3 = int(p.J3);
-    fa.nbB = dB ? int(ceil_div(p.J2 * p.I2, 128)) : 0;
-    fa.nbC = dC ? int(ceil_div(p.J3 * p.I3, 128)) : 0;
-    const bool fin = dA || dB || dC;
+    fa.nbB = dB ? int(ceil_div(p.J2 * p.I2, 64)) : 0;
+    fa.nbC = dC ? int(ceil_div(p.J3 * p.I3, 64)) : 0;
     switch (p.ncg) {
-        case 2: return run_fused_ncg<2>(fa, dX != nullptr, fin, st);
-        case 4: return run_fused_ncg<4>(fa, dX != nullptr, fin, st);
-        case 8: return run_fused_ncg<8>(fa, dX != nullptr, fin, st);
+        case 4: return run_fused_ncg<4>(fa, st);
+        case 8: return run_fused_ncg<8>(fa, st);
         default: return TTM_ERR_UNSUPPORTED;
     }
 }

@@ -31,13 +31,15 @@ SHAPES = [((6, 7, 8), (3, 5, 4)), ((37, 70, 65), (20, 9, 33)), ((1, 1, 1), (1, 1
           ((300, 7, 320), (2, 3, 20)),
           # ... and J2 <= 32 with I2 a multiple of 64: V and R on streaming kernels too
           ((5, 64, 128), (6, 9, 32)), ((3, 192, 64), (4, 32, 12)),
-          # float32 with J <= 32, I3 in {128, 256, 512}, I2 a multiple of 4:
-          # the fused kernels (one, two and eight 16-row blocks per chunk;
-          # ragged last chunks, a single chunk, many slabs, padded J)
-          ((3, 40, 256), (5, 7, 30)), ((2, 100, 512), (32, 32, 32)), ((4, 132, 128), (1, 17, 3)),
-          ((1, 4, 256), (2, 2, 2)), ((7, 256, 256), (32, 32, 32)), ((300, 8, 128), (3, 4, 5))]
+          # float32 with J <= 32, I3 in {256, 512}, I2 a multiple of 4: the
+          # fused kernels (two and one 16-row blocks per chunk; ragged last
+          # chunks, a single chunk, many slabs, padded J); I3 = 64 and 128 take
+          # the product sequence
+          ((3, 40, 256), (5, 7, 30)), ((2, 100, 512), (32, 32, 32)), ((4, 132, 256), (1, 17, 3)),
+          ((1, 4, 256), (2, 2, 2)), ((7, 256, 256), (32, 32, 32)), ((300, 8, 512), (3, 4, 5)),
+          ((2, 100, 64), (32, 32, 32)), ((4, 132, 128), (1, 17, 3))]
 
-FUSED_SHAPES = [((3, 40, 256), (5, 7, 30)), ((2, 100, 512), (32, 32, 32)), ((4, 132, 128), (1, 17, 3))]
+FUSED_SHAPES = [((3, 40, 256), (5, 7, 30)), ((2, 100, 512), (32, 32, 32)), ((4, 132, 256), (1, 17, 3))]
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: f"I{s[0]}J{s[1]}")
