@@ -24,6 +24,8 @@
 // the algorithmic minimum is two.
 #include <math.h>
 
+#include <algorithm>
+
 #include "ttm_device.hpp"
 #include "ttm_host.hpp"
 
@@ -382,6 +384,188 @@ __global__ void __launch_bounds__(256) k_compact_rows_full(const CompactArgs a, 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Single-pass sweep.  A_c = tridiag(alpha, 1, alpha) with periodic corners is
+// circulant and, for |alpha| < 1/2, factors as
+//     A_c = c (I + rho S)(I + rho S^T),  rho = (1 - sqrt(1 - 4 alpha^2)) / (2 alpha),
+//     c = 1 / (1 + rho^2),  (S y)_j = y_{j+1} (indices mod n),
+// so A_c y = d is a cyclic forward recursion f_j = d_j - rho f_{j-1} followed
+// by a cyclic backward recursion g_j = f_j - rho g_{j+1}, y = (1 + rho^2) g.
+// |rho| < 1 (diagonal dominance, the premise of Sec. 4.2's DistD2): a value
+// K steps back (or ahead) enters with weight rho^K, below the rounding unit
+// for K >= KT, so each recursion starts K points early from zero and every
+// output needs the input only up to K points away.  One read of X and one
+// write of Y per point, no intermediate in memory.
+// ---------------------------------------------------------------------------
+struct OnePassArgs {
+    int64_t n, stride, nfib, i3, s12;
+    int mode;
+    double ca, cb, rho, scale;   // a / (2h), b / (4h), rho, 1 + rho^2
+};
+
+// Modes 1 and 2: one lane per fiber (neighbouring lanes read neighbouring
+// addresses at every step).  The forward recursion runs K + L points ahead of
+// the outputs in a register window F[K + L]; every L points the backward
+// recursion runs over the window from its far end and the first L values are
+// stored.  The stencil reads of a block are issued before its recursion.
+template <typename T, int K, int L>
+__global__ void __launch_bounds__(256) k_compact_lines(const OnePassArgs a, const T *__restrict__ X,
+                                                       T *__restrict__ Y) {
+    const int64_t n = a.n, s = a.stride;
+    const T ca = T(a.ca), cb = T(a.cb), rho = T(a.rho), scale = T(a.scale);
+    for (int64_t f = int64_t(blockIdx.x) * 256 + threadIdx.x; f < a.nfib; f += int64_t(gridDim.x) * 256) {
+        const int64_t base = a.mode == 1 ? f : (f / a.i3) * a.s12 + f % a.i3;
+        const T *u = X + base;
+        T *y = Y + base;
+        // the stencil stream: point j needs u_{j-2} .. u_{j+2} (mod n); jn is
+        // the index (mod n) of the next value to read
+        int64_t jn = n - K + 2;
+        T um2 = u[(n - K - 2) * s], um1 = u[(n - K - 1) * s], uc = u[(n - K) * s], up1 = u[(n - K + 1) * s];
+        auto next_index = [&]() __attribute__((always_inline)) {
+            const int64_t j = jn;
+            jn = jn + 1 == n ? 0 : jn + 1;
+            return j;
+        };
+        auto step = [&](T up2) __attribute__((always_inline)) {
+            const T d = ca * (up1 - um1) + cb * (up2 - um2);
+            um2 = um1;
+            um1 = uc;
+            uc = up1;
+            up1 = up2;
+            return d;
+        };
+        // forward warm-up over the K points before point 0
+        T fprev = T(0);
+#pragma unroll 8
+        for (int t = 0; t < K; ++t) fprev = step(u[next_index() * s]) - rho * fprev;
+        // F[i] = f_{b + i}: first f_0 .. f_{K-1}
+        T F[K + L];
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+            fprev = step(u[next_index() * s]) - rho * fprev;
+            F[t] = fprev;
+        }
+        for (int64_t b = 0; b < n; b += L) {
+            T v[L];
+#pragma unroll
+            for (int t = 0; t < L; ++t) v[t] = u[next_index() * s];
+#pragma unroll
+            for (int t = 0; t < L; ++t) {
+                fprev = step(v[t]) - rho * fprev;
+                F[K + t] = fprev;
+            }
+            T g = T(0);
+#pragma unroll
+            for (int i = K + L - 1; i >= L; --i) g = F[i] - rho * g;
+            T out[L];
+#pragma unroll
+            for (int i = L - 1; i >= 0; --i) {
+                g = F[i] - rho * g;
+                out[i] = scale * g;
+            }
+#pragma unroll
+            for (int i = 0; i < L; ++i)
+                if (b + i < n) y[(b + i) * s] = out[i];
+#pragma unroll
+            for (int i = 0; i < K; ++i) F[i] = F[i + L];
+        }
+    }
+}
+
+// Mode 3: fibers are contiguous rows.  A wave takes one row at a time: the row
+// comes into LDS with coalesced 16-byte loads (word l of each 64-word group),
+// lane l computes points [c l, c l + c) (c = n / 64): the forward recursion
+// from K points before its range, its f values to LDS; then the backward
+// recursion from K points past its range over the f values of the lanes
+// after it, its y values to LDS; the row leaves with coalesced stores.  Row
+// positions are padded by one element every c (lane ranges start in
+// different banks).  The next row's words are loaded while a row is
+// computed.
+// Rows of n = 64 C points, C a power of two, n <= 256 VE (at most four
+// 16-byte words per lane); the recursions are unrolled.
+template <typename T, int K, int C>
+__global__ void __launch_bounds__(256) k_compact_rows1p(const OnePassArgs a, const T *__restrict__ X,
+                                                        T *__restrict__ Y) {
+    constexpr int VE = 16 / int(sizeof(T)), WPL = 4;
+    constexpr int lc = C == 1 ? 0 : C == 2 ? 1 : C == 4 ? 2 : C == 8 ? 3 : 4;
+    static_assert((1 << lc) == C && 64 * C <= 256 * VE, "row length");
+    extern __shared__ __align__(16) unsigned char smem_1p[];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    constexpr int n = 64 * C, c = C, nw = n / VE;
+    constexpr int padded = n + 64;
+    T *ub = reinterpret_cast<T *>(smem_1p) + wave * 2 * padded;
+    T *fb = ub + padded;
+    auto pos = [&](int j) __attribute__((always_inline)) { return j + (j >> lc); };
+    const T ca = T(a.ca), cb = T(a.cb), rho = T(a.rho), scale = T(a.scale);
+    const int64_t wstride = int64_t(gridDim.x) * 4;
+    int64_t r = int64_t(blockIdx.x) * 4 + wave;
+    V16 buf[WPL];
+    auto fetch = [&](int64_t row) __attribute__((always_inline)) {
+        const u32x4 *src = reinterpret_cast<const u32x4 *>(X + row * n);
+#pragma unroll
+        for (int i = 0; i < WPL; ++i)
+            if (lane + 64 * i < nw) buf[i].u = __builtin_nontemporal_load(src + lane + 64 * i);
+    };
+    if (r < a.nfib) fetch(r);
+    for (; r < a.nfib; r += wstride) {
+        wave_sync();
+#pragma unroll
+        for (int i = 0; i < WPL; ++i)
+            if (lane + 64 * i < nw) {
+                const int j0 = (lane + 64 * i) * VE;
+#pragma unroll
+                for (int e = 0; e < VE; ++e) ub[pos(j0 + e)] = reinterpret_cast<const T *>(&buf[i])[e];
+            }
+        if (r + wstride < a.nfib) fetch(r + wstride);
+        wave_sync();
+        const int j0 = c * lane;
+        // forward: from K points before this lane's range (mod n)
+        {
+            int j = j0 - K;
+            auto U = [&](int k) __attribute__((always_inline)) {   // k in [-K - 2, n + 1]
+                const int m = k < 0 ? k + n : (k >= n ? k - n : k);
+                return ub[pos(m)];
+            };
+            T um2 = U(j - 2), um1 = U(j - 1), uc = U(j), up1 = U(j + 1);
+            T f = T(0);
+#pragma unroll
+            for (int t = 0; t < K + c; ++t, ++j) {
+                const T up2 = U(j + 2);
+                f = ca * (up1 - um1) + cb * (up2 - um2) - rho * f;
+                um2 = um1;
+                um1 = uc;
+                uc = up1;
+                up1 = up2;
+                if (t >= K) fb[pos(j)] = f;
+            }
+        }
+        wave_sync();
+        // backward: from K points past this lane's range (mod n); y overwrites u
+        {
+            T g = T(0);
+#pragma unroll
+            for (int t = K + c - 1; t >= 0; --t) {
+                int m = j0 + t;
+                if (m >= n) m -= n;
+                g = fb[pos(m)] - rho * g;
+                if (t < c) ub[pos(m)] = scale * g;
+            }
+        }
+        wave_sync();
+        u32x4 *dst = reinterpret_cast<u32x4 *>(Y + r * n);
+#pragma unroll
+        for (int i = 0; i < WPL; ++i)
+            if (lane + 64 * i < nw) {
+                const int jw = (lane + 64 * i) * VE;
+                V16 v;
+#pragma unroll
+                for (int e = 0; e < VE; ++e) reinterpret_cast<T *>(&v)[e] = ub[pos(jw + e)];
+                __builtin_nontemporal_store(v.u, dst + lane + 64 * i);
+            }
+    }
+}
+
 }  // namespace
 
 }  // namespace ttm
@@ -457,13 +641,58 @@ int ttm_compact_apply(const int64_t *dims, int mode, const void *X, void *Y, int
         if (int rc = ensure_lds_limit(fn, bytes, attr_set[k][f])) return rc;
     }
     int rc = TTM_OK;
+    // single pass where the recursions' truncation is below the rounding unit
+    // (coefficients for the exact sweeps are still prepared when asked, so a
+    // later prepared call may take either path)
+    const int KT = dtype == TTM_F64 ? 40 : 20;
+    const double alpha = coef->alpha;
+    const double rho = alpha == 0.0 ? 0.0 : (1.0 - sqrt(1.0 - 4.0 * alpha * alpha)) / (2.0 * alpha);
+    const double unit = dtype == TTM_F64 ? 0x1p-53 : 0x1p-24;
+    bool onepass = pow(fabs(rho), double(KT)) <= 0.5 * unit && n >= 2 * KT;
+    int lc = 0;
+    if (mode == 3) {
+        const int64_t VE = int64_t(16 / es);
+        while ((int64_t(64) << lc) < n) ++lc;
+        onepass = onepass && n == (int64_t(64) << lc) && n <= 256 * VE && aligned(X, 16) && aligned(Y, 16);
+    }
+    OnePassArgs oa;
+    oa.n = n;
+    oa.stride = a.stride;
+    oa.nfib = a.nfib;
+    oa.i3 = a.i3;
+    oa.s12 = a.s12;
+    oa.mode = mode;
+    oa.ca = a.ca;
+    oa.cb = a.cb;
+    oa.rho = rho;
+    oa.scale = 1.0 + rho * rho;
+    const size_t lds1p = 4 * 2 * size_t(n + 64) * es;
+    const unsigned blocks1p = unsigned(std::min<int64_t>(ceil_div(a.nfib, 4), int64_t(device_cu_count()) * 4));
     if (dtype == TTM_F64) {
         if (!prepared)
             rc = launch("ttm_compact_prep", st, [&] {
                 hipLaunchKernelGGL(k_compact_prep<double>, dim3(1), dim3(64), prep_lds, st, n, coef->alpha,
                                    static_cast<double *>(ws));
             });
-        if (rc == TTM_OK && mode == 3)
+        if (rc == TTM_OK && onepass && mode == 3)
+            rc = launch("ttm_compact", st, [&] {
+                auto args = [&](auto kern) {
+                    hipLaunchKernelGGL(kern, dim3(blocks1p), dim3(256), lds1p, st, oa, static_cast<const double *>(X),
+                                       static_cast<double *>(Y));
+                };
+                switch (lc) {
+                    case 0: args(k_compact_rows1p<double, 40, 1>); break;
+                    case 1: args(k_compact_rows1p<double, 40, 2>); break;
+                    case 2: args(k_compact_rows1p<double, 40, 4>); break;
+                    default: args(k_compact_rows1p<double, 40, 8>); break;
+                }
+            });
+        else if (rc == TTM_OK && onepass)
+            rc = launch("ttm_compact", st, [&] {
+                hipLaunchKernelGGL((k_compact_lines<double, 40, 8>), dim3(blocks), dim3(256), 0, st, oa,
+                                   static_cast<const double *>(X), static_cast<double *>(Y));
+            });
+        else if (rc == TTM_OK && mode == 3)
             rc = launch("ttm_compact", st, [&] {
                 hipLaunchKernelGGL(full_tiles ? k_compact_rows_full<double> : k_compact_rows<double>, dim3(row_blocks), dim3(256),
                                    4 * RowsCfg<double>::WAVE_ELEMS * sizeof(double), st, a,
@@ -481,7 +710,26 @@ int ttm_compact_apply(const int64_t *dims, int mode, const void *X, void *Y, int
                 hipLaunchKernelGGL(k_compact_prep<float>, dim3(1), dim3(64), prep_lds, st, n, coef->alpha,
                                    static_cast<float *>(ws));
             });
-        if (rc == TTM_OK && mode == 3)
+        if (rc == TTM_OK && onepass && mode == 3)
+            rc = launch("ttm_compact", st, [&] {
+                auto args = [&](auto kern) {
+                    hipLaunchKernelGGL(kern, dim3(blocks1p), dim3(256), lds1p, st, oa, static_cast<const float *>(X),
+                                       static_cast<float *>(Y));
+                };
+                switch (lc) {
+                    case 0: args(k_compact_rows1p<float, 20, 1>); break;
+                    case 1: args(k_compact_rows1p<float, 20, 2>); break;
+                    case 2: args(k_compact_rows1p<float, 20, 4>); break;
+                    case 3: args(k_compact_rows1p<float, 20, 8>); break;
+                    default: args(k_compact_rows1p<float, 20, 16>); break;
+                }
+            });
+        else if (rc == TTM_OK && onepass)
+            rc = launch("ttm_compact", st, [&] {
+                hipLaunchKernelGGL((k_compact_lines<float, 20, 8>), dim3(blocks), dim3(256), 0, st, oa,
+                                   static_cast<const float *>(X), static_cast<float *>(Y));
+            });
+        else if (rc == TTM_OK && mode == 3)
             rc = launch("ttm_compact", st, [&] {
                 hipLaunchKernelGGL(full_tiles ? k_compact_rows_full<float> : k_compact_rows<float>, dim3(row_blocks), dim3(256),
                                    4 * RowsCfg<float>::WAVE_ELEMS * sizeof(float), st, a,

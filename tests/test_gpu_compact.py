@@ -46,6 +46,37 @@ def test_compact_matches_oracle(shape, dt):
             check(X, mode, 0.7 / shape[mode - 1], dt)
 
 
+# fibers long enough for the single-pass sweep (at least twice the
+# recursion's truncation length: 80 points in float64, 40 in float32) on
+# every mode, including mode-3 rows of 64 c points (c = 1 .. 16) and the
+# shortest admissible fibers; the shorter fibers above take the exact sweeps
+ONEPASS_SHAPES = [(512, 4, 16), (4, 512, 16), (4, 16, 512), (80, 3, 5), (40, 6, 64), (8, 8, 1024), (3, 5, 128)]
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("shape", ONEPASS_SHAPES, ids=lambda s: "x".join(map(str, s)))
+def test_compact_single_pass_matches_oracle(shape, dt):
+    rng = np.random.default_rng(sum(shape) + 1)
+    X = rng.standard_normal(shape)
+    for mode in (1, 2, 3):
+        if shape[mode - 1] >= 3:
+            check(X, mode, 2 * np.pi / shape[mode - 1], dt)
+
+
+@pytest.mark.parametrize("alpha", [0.0, -0.3, 0.45])
+def test_compact_single_pass_other_alpha(alpha):
+    """Other diagonally dominant LHS coefficients: alpha = 0 (explicit
+    stencil), a negative alpha, and alpha = 0.45 (rho = 0.63, whose float64
+    truncation would need about 80 points: the exact sweeps run)."""
+    rng = np.random.default_rng(17)
+    X = rng.standard_normal((96, 8, 128))
+    for mode in (1, 3):
+        h = 0.01
+        Y, Xd = gpu_apply(X, mode, alpha, A, B, h)
+        ref = oracle.compact6_apply(X, mode, alpha, A, B, h)
+        assert pins.rel_fro(Y, ref) <= TOL[torch.float64], (mode, alpha)
+
+
 @pytest.mark.parametrize("dt", [torch.float64, torch.float32], ids=["f64", "f32"])
 def test_compact_closed_form(dt):
     fn = lambda X, mode, alpha, a, b, h: gpu_apply(X, mode, alpha, a, b, h, dt)[0]
