@@ -266,9 +266,17 @@ int ttm_batched_plan_config(const ttm_batched_plan *plan, int *out);
  * for every fiber along `mode`, indices taken modulo n = dims[mode-1], i.e.
  * Y = X x_mode D with D = A_c^-1 B_c (A_c the cyclic tridiagonal left side,
  * B_c the cyclic five-point right side), evaluated without forming D: the
- * right-hand side is built on the fly and solved as a cyclic tridiagonal
- * system (Sec. 2.1, the periodic Thomas algorithm).  The paper's values are
- * alpha = 1/3, a = 14/9, b = 1/9.
+ * right-hand side is built on the fly and the cyclic tridiagonal system
+ * (Sec. 2.1) is solved in one of two ways.  Fibers of at least 2K points
+ * (K = 40 for F64, 20 for F32) whose coefficient alpha makes rho^K below the
+ * rounding unit (rho = (1 - sqrt(1 - 4 alpha^2)) / (2 alpha); alpha = 1/3
+ * gives 0.382) take a single pass: A_c factors as a product of two cyclic
+ * first-order operators whose inverses are recursions that forget their
+ * start after K points (the diagonal dominance of Sec. 4.2), so each point
+ * is read once and written once; the result equals the exact solve up to
+ * rounding.  Other fibers take the periodic Thomas algorithm (forward and
+ * backward sweeps through Y).  The paper's values are alpha = 1/3,
+ * a = 14/9, b = 1/9.
  */
 typedef struct {
     double alpha, a, b, h;   /* |alpha| < 1/2 (diagonal dominance); h != 0 */
@@ -286,8 +294,9 @@ size_t ttm_compact_workspace_size(int64_t n, int dtype);
  *   coef   host pointer, read during the call
  *   ws     device workspace of ttm_compact_workspace_size(dims[mode-1], dtype)
  *          bytes (16-byte aligned); it holds the fiber-independent coefficients
- *          of the solve (the preprocessing the paper does once per operator,
- *          Sec. 4.2), computed on the device on `stream`
+ *          of the Thomas sweeps (the preprocessing the paper does once per
+ *          operator, Sec. 4.2), computed on the device on `stream`; the
+ *          single pass does not read it
  *   prepared  0: compute the coefficients into ws first (a short sequential
  *          kernel, about 0.1 ms for 512 points); 1: ws already holds them
  *          from an earlier call with the same fiber length, coef and dtype

@@ -1,27 +1,32 @@
 // ttm_compact.hip -- the compact sixth-order first derivative of Sec. 4.2,
 // Eq. (cfds), applied along one mode of a periodic 3-way field without forming
-// D = A_c^-1 B_c.  Per fiber, the five-point right-hand side is built on the
-// fly and fused with the forward pass of a cyclic tridiagonal solve (Sec. 2.1,
-// the periodic Thomas algorithm, here as a Sherman-Morrison correction of one
-// tridiagonal solve); the correction's scalar is accumulated during the
-// forward pass, so one backward pass finishes the solve.
+// D = A_c^-1 B_c.  Two solvers of the cyclic tridiagonal system:
 //
-// Splitting (gamma = -1): A_c = T + p q^T, T tridiagonal with alpha beside the
-// diagonal and diagonal 1 except T_00 = 1 - gamma, T_{n-1,n-1} = 1 - alpha^2 /
-// gamma; p = (gamma, 0, .., 0, alpha), q = (1, 0, .., 0, alpha / gamma).  With
-// T y = d and T z = p the solution is x = y - [q.y / (1 + q.z)] z.  The
-// fiber-independent data -- inv_j and cp_j of T's forward pass, z, and weights
-// w_j with y_0 = sum_j w_j y'_j (y' the forward-pass values) -- come from one
-// device thread in double precision before the sweep.
+// Single pass (fibers of at least 2K points, K = 40 in float64, 20 in float32,
+// and |alpha| small enough that rho^K is below the rounding unit): the
+// circulant factorization of A_c below turns the solve into two first-order
+// recursions that forget their start after K points, so each point is read
+// once and written once (the algorithmic two transfers).
 //
-// Layout: one lane per fiber, as the paper gives each GPU thread one line of a
-// group of SZ lines (Sec. 4.1).  Row-major X makes the fibers of modes 1 and 2
-// interleaved already (lane f and f+1 read neighbouring addresses at every
-// step); mode-3 fibers are contiguous rows, read with a stride of n elements
-// per lane and served by the L1/L2 lines they share across steps.  The forward
+// Exact sweeps (shorter fibers): the five-point right-hand side is built on
+// the fly and fused with the forward pass of a cyclic tridiagonal solve
+// (Sec. 2.1, the periodic Thomas algorithm, here as a Sherman-Morrison
+// correction of one tridiagonal solve); the correction's scalar is
+// accumulated during the forward pass, so one backward pass finishes the
+// solve.  Splitting (gamma = -1): A_c = T + p q^T, T tridiagonal with alpha
+// beside the diagonal and diagonal 1 except T_00 = 1 - gamma, T_{n-1,n-1} =
+// 1 - alpha^2 / gamma; p = (gamma, 0, .., 0, alpha), q = (1, 0, .., 0, alpha /
+// gamma).  With T y = d and T z = p the solution is x = y - [q.y / (1 + q.z)]
+// z.  The fiber-independent data -- inv_j and cp_j of T's forward pass, z, and
+// weights w_j with y_0 = sum_j w_j y'_j (y' the forward-pass values) -- come
+// from one device thread in double precision before the sweep.  The forward
 // pass stores y' into Y and the backward pass turns it into the solution in
-// place, so each point moves four times (read X, write y', read y', write Y);
-// the algorithmic minimum is two.
+// place: four transfers per point.
+//
+// Layout: one lane per fiber for modes 1 and 2, as the paper gives each GPU
+// thread one line of a group of SZ lines (Sec. 4.1): row-major X makes those
+// fibers interleaved already (lane f and f+1 read neighbouring addresses at
+// every step).  Mode-3 fibers are contiguous rows, moved through LDS tiles.
 #include <math.h>
 
 #include <algorithm>
