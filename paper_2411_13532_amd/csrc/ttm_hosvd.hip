@@ -9,12 +9,13 @@
 // workgroup, G resident in LDS (I_n <= 128): each sweep visits every pair
 // (p, q) once, in rounds of I_n / 2 disjoint pairs (the round-robin
 // schedule), every round one set of plane rotations applied to the rows,
-// then the columns, of G and to the columns of the eigenvector matrix V.
-// Sweeps repeat until the off-diagonal mass is below 1e-30 of the diagonal's
-// (at most 40).  The eigenvalues sorted in decreasing order select the
-// columns of V that become the factor's rows, each with its entry of largest
-// magnitude made positive (the sign convention that makes the vector of a
-// simple eigenvalue unique).
+// then the columns, of G and to the eigenvector matrix.
+// Sweeps repeat until the off-diagonal mass is below (I_n u)^2 of the
+// diagonal's, u = 2^-53 (at most 40): rounding alone keeps it near I_n u^2,
+// so a fixed tighter bound would run every sweep.  The eigenvalues sorted in
+// decreasing order select the eigenvectors that become the factor's rows,
+// each with its entry of largest magnitude made positive (the sign
+// convention that makes the vector of a simple eigenvalue unique).
 #include <algorithm>
 #include <cstring>
 
@@ -28,24 +29,30 @@ constexpr int EIG_NMAX = 128;
 constexpr int EIG_THREADS = 1024;
 constexpr int EIG_MAX_SWEEPS = 40;
 
-// V (n x n, column k = eigenvector k) and sorted outputs: rows r < J of U
-// (J x n) and the n eigenvalues in decreasing order (nullable).
-__global__ void __launch_bounds__(EIG_THREADS) k_sym_jacobi(const double *G, int n, double *V, int J, double *U,
+// Vt (n x n in global memory, row k = eigenvector k: the rotations then
+// touch two rows, contiguous in memory) and sorted outputs: rows r < J of U
+// (J x n) and the n eigenvalues in decreasing order (nullable).  A sits in
+// LDS with rows padded to EIG_LDA doubles, so that the column updates of a
+// round (32 consecutive rows of one column per half-wave) hit distinct banks.
+// Thread t of a rotation phase takes pair t / 16 and elements (t % 16) + 16 m.
+constexpr int EIG_LDA = EIG_NMAX + 1;
+__global__ void __launch_bounds__(EIG_THREADS) k_sym_jacobi(const double *G, int n, double *Vt, int J, double *U,
                                                              double *evals) {
-    __shared__ double A[EIG_NMAX * EIG_NMAX];
+    __shared__ double A[EIG_NMAX * EIG_LDA];
     __shared__ double rc[EIG_NMAX / 2 + 1], rs[EIG_NMAX / 2 + 1];
     __shared__ int rp[EIG_NMAX / 2 + 1], rq[EIG_NMAX / 2 + 1];
     __shared__ double red[EIG_THREADS / 64][2];
     __shared__ int order[EIG_NMAX];
     __shared__ int done;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int nn = n * n;
-    for (int e = tid; e < nn; e += EIG_THREADS) {
-        A[e] = G[e];
-        V[e] = (e / n) == (e % n) ? 1.0 : 0.0;
+    for (int e = tid; e < n * n; e += EIG_THREADS) {
+        const int i = e / n, j = e - i * n;
+        A[i * EIG_LDA + j] = G[e];
+        Vt[e] = i == j ? 1.0 : 0.0;
     }
     const int m = n + (n & 1);          // players of the round-robin (one idle slot when n is odd)
     const int np = m / 2;
+    const int pk = tid >> 4, e0 = tid & 15;   // pair and first element of this thread
     __syncthreads();
     for (int sweep = 0; sweep < EIG_MAX_SWEEPS; ++sweep) {
         for (int r = 0; r < m - 1; ++r) {
@@ -56,9 +63,9 @@ __global__ void __launch_bounds__(EIG_THREADS) k_sym_jacobi(const double *G, int
                 else { p = (r + tid) % (m - 1); q = (r - tid + (m - 1)) % (m - 1); }
                 double c = 1.0, s = 0.0;
                 if (p < n && q < n) {
-                    const double apq = A[p * n + q];
+                    const double apq = A[p * EIG_LDA + q];
                     if (apq != 0.0) {
-                        const double tau = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
+                        const double tau = (A[q * EIG_LDA + q] - A[p * EIG_LDA + p]) / (2.0 * apq);
                         const double at = fabs(tau);
                         const double t = at > 1e150 ? 0.5 / tau
                                                     : (tau >= 0.0 ? 1.0 : -1.0) / (at + sqrt(1.0 + tau * tau));
@@ -72,39 +79,53 @@ __global__ void __launch_bounds__(EIG_THREADS) k_sym_jacobi(const double *G, int
                 rs[tid] = s;
             }
             __syncthreads();
+            const int p = pk < np ? rp[pk] : n, q = pk < np ? rq[pk] : n;
+            const bool live = p < n && q < n;
+            const double c = live ? rc[pk] : 1.0, s = live ? rs[pk] : 0.0;
+            // rows p and q of Vt: every load issued before the updates (one
+            // memory latency per round), stored after the barrier below
+            constexpr int EPT = EIG_NMAX / 16;   // elements per thread
+            double vp[EPT], vq[EPT];
+            if (live)
+#pragma unroll
+                for (int u = 0; u < EPT; ++u) {
+                    const int i = e0 + 16 * u;
+                    vp[u] = i < n ? Vt[p * n + i] : 0.0;
+                    vq[u] = i < n ? Vt[q * n + i] : 0.0;
+                }
             // rows p and q of A
-            for (int w = tid; w < np * n; w += EIG_THREADS) {
-                const int k = w / n, j = w - k * n;
-                const int p = rp[k], q = rq[k];
-                if (p < n && q < n) {
-                    const double c = rc[k], s = rs[k];
-                    const double ap = A[p * n + j], aq = A[q * n + j];
-                    A[p * n + j] = c * ap - s * aq;
-                    A[q * n + j] = s * ap + c * aq;
+            if (live)
+#pragma unroll
+                for (int u = 0; u < EPT; ++u) {
+                    const int j = e0 + 16 * u;
+                    if (j < n) {
+                        const double ap = A[p * EIG_LDA + j], aq = A[q * EIG_LDA + j];
+                        A[p * EIG_LDA + j] = c * ap - s * aq;
+                        A[q * EIG_LDA + j] = s * ap + c * aq;
+                    }
                 }
-            }
             __syncthreads();
-            // columns p and q of A and of V
-            for (int w = tid; w < np * n; w += EIG_THREADS) {
-                const int k = w / n, i = w - k * n;
-                const int p = rp[k], q = rq[k];
-                if (p < n && q < n) {
-                    const double c = rc[k], s = rs[k];
-                    const double ap = A[i * n + p], aq = A[i * n + q];
-                    A[i * n + p] = c * ap - s * aq;
-                    A[i * n + q] = s * ap + c * aq;
-                    const double vp = V[i * n + p], vq = V[i * n + q];
-                    V[i * n + p] = c * vp - s * vq;
-                    V[i * n + q] = s * vp + c * vq;
+            // columns p and q of A
+            if (live)
+#pragma unroll
+                for (int u = 0; u < EPT; ++u) {
+                    const int i = e0 + 16 * u;
+                    if (i < n) {
+                        const double ap = A[i * EIG_LDA + p], aq = A[i * EIG_LDA + q];
+                        A[i * EIG_LDA + p] = c * ap - s * aq;
+                        A[i * EIG_LDA + q] = s * ap + c * aq;
+                        Vt[p * n + i] = c * vp[u] - s * vq[u];
+                        Vt[q * n + i] = s * vp[u] + c * vq[u];
+                    }
                 }
-            }
             __syncthreads();
         }
         // off-diagonal and diagonal mass, fixed-order reduction
         double off = 0.0, dia = 0.0;
-        for (int e = tid; e < nn; e += EIG_THREADS) {
-            const double v = A[e];
-            if (e / n == e % n) dia += v * v;
+        for (int e = tid; e < n * n; e += EIG_THREADS) {
+            const int i = e / n, j = e - i * n;
+            const double v = A[i * EIG_LDA + j];
+            if (i == j) dia += v * v;
             else off += v * v;
         }
         for (int o = 32; o > 0; o >>= 1) {
@@ -116,30 +137,33 @@ __global__ void __launch_bounds__(EIG_THREADS) k_sym_jacobi(const double *G, int
         if (tid == 0) {
             double so = 0.0, sd = 0.0;
             for (int w = 0; w < EIG_THREADS / 64; ++w) { so += red[w][0]; sd += red[w][1]; }
-            done = so <= 1e-30 * sd;
+            // rounding keeps the off-diagonal mass near n u^2 of the
+            // diagonal's (u = 2^-53): stop at (n u)^2, a hundred times above
+            const double nu = double(n) * 0x1p-53;
+            done = so <= nu * nu * sd;
         }
         __syncthreads();
         if (done) break;
     }
     // decreasing order of the eigenvalues (ties: lower index first)
     if (tid < n) {
-        const double li = A[tid * n + tid];
+        const double li = A[tid * EIG_LDA + tid];
         int rank = 0;
         for (int j = 0; j < n; ++j) {
-            const double lj = A[j * n + j];
+            const double lj = A[j * EIG_LDA + j];
             rank += (lj > li || (lj == li && j < tid)) ? 1 : 0;
         }
         order[rank] = tid;
     }
     __syncthreads();
-    if (evals && tid < n) evals[tid] = A[order[tid] * n + order[tid]];
-    // factor rows: one wave per row, sign fixed by the entry of largest magnitude
+    if (evals && tid < n) evals[tid] = A[order[tid] * EIG_LDA + order[tid]];
+// factor rows: one wave per row, sign fixed by the entry of largest magnitude
     for (int row = wave; row < J; row += EIG_THREADS / 64) {
         const int col = order[row];
         double best = -1.0;
         int bi = n;
         for (int i = lane; i < n; i += 64) {
-            const double a = fabs(V[i * n + col]);
+            const double a = fabs(Vt[col * n + i]);
             if (a > best || (a == best && i < bi)) { best = a; bi = i; }
         }
         for (int o = 32; o > 0; o >>= 1) {
@@ -147,8 +171,8 @@ __global__ void __launch_bounds__(EIG_THREADS) k_sym_jacobi(const double *G, int
             const int oi = __shfl_xor(bi, o);
             if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
         }
-        const double sgn = V[bi * n + col] < 0.0 ? -1.0 : 1.0;
-        for (int i = lane; i < n; i += 64) U[int64_t(row) * n + i] = sgn * V[i * n + col];
+        const double sgn = Vt[col * n + bi] < 0.0 ? -1.0 : 1.0;
+        for (int i = lane; i < n; i += 64) U[int64_t(row) * n + i] = sgn * Vt[col * n + i];
     }
 }
 
