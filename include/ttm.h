@@ -314,7 +314,8 @@ int ttm_compact_apply(const int64_t *dims, int mode, const void *X, void *Y, int
  * mode n, the J[n] leading left singular vectors of the unfolding X_(n), as
  * the rows of an J[n] x I[n] factor, computed in FP64 on the GPU: the Gram
  * matrix X_(n) X_(n)^T on the FP64 matrix cores, then its symmetric
- * eigendecomposition by the cyclic Jacobi method in one workgroup.  Rows come
+ * eigendecomposition by the cyclic Jacobi method (one workgroup per mode, the
+ * three modes in one launch).  Rows come
  * in decreasing order of their eigenvalue (squared singular value), each
  * with its entry of largest magnitude positive.  X x1 A x2 B x3 C with these
  * factors (ttm_chain) is the Tucker core.

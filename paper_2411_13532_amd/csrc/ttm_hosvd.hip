@@ -36,8 +36,17 @@ constexpr int EIG_MAX_SWEEPS = 40;
 // round (32 consecutive rows of one column per half-wave) hit distinct banks.
 // Thread t of a rotation phase takes pair t / 16 and elements (t % 16) + 16 m.
 constexpr int EIG_LDA = EIG_NMAX + 1;
-__global__ void __launch_bounds__(EIG_THREADS) k_sym_jacobi(const double *G, int n, double *Vt, int J, double *U,
-                                                             double *evals) {
+// One workgroup per mode (the three solves are independent).
+struct JacobiArgs {
+    const double *G[3];
+    double *Vt[3], *U[3], *evals[3];
+    int n[3], J[3];
+};
+__global__ void __launch_bounds__(EIG_THREADS) k_sym_jacobi(const JacobiArgs ja) {
+    const int mode = blockIdx.x;
+    const double *G = ja.G[mode];
+    double *Vt = ja.Vt[mode], *U = ja.U[mode], *evals = ja.evals[mode];
+    const int n = ja.n[mode], J = ja.J[mode];
     __shared__ double A[EIG_NMAX * EIG_LDA];
     __shared__ double rc[EIG_NMAX / 2 + 1], rs[EIG_NMAX / 2 + 1];
     __shared__ int rp[EIG_NMAX / 2 + 1], rq[EIG_NMAX / 2 + 1];
@@ -179,7 +188,7 @@ __global__ void __launch_bounds__(EIG_THREADS) k_sym_jacobi(const double *G, int
 struct HosvdPlan {
     int64_t nmax;
     int ks[3];
-    size_t off_G, off_V, off_P, total;
+    size_t off_G[3], off_V[3], off_P, total;
 };
 
 static void hosvd_plan(const ttm_shape &s, HosvdPlan &p) {
@@ -195,10 +204,12 @@ static void hosvd_plan(const ttm_shape &s, HosvdPlan &p) {
         p.ks[n] = int(k);
         kmax = std::max(kmax, p.ks[n]);
     }
-    const size_t nn = size_t(p.nmax * p.nmax) * 8;
-    p.off_G = 0;
-    p.off_V = (nn + 255) & ~size_t(255);
-    p.off_P = p.off_V + ((nn + 255) & ~size_t(255));
+    const size_t nn = size_t(p.nmax * p.nmax) * 8, nn_al = (nn + 255) & ~size_t(255);
+    for (int n = 0; n < 3; ++n) {
+        p.off_G[n] = size_t(n) * nn_al;
+        p.off_V[n] = size_t(3 + n) * nn_al;
+    }
+    p.off_P = 6 * nn_al;
     p.total = p.off_P + (kmax > 1 ? size_t(kmax) * nn : 0);
 }
 
@@ -286,20 +297,24 @@ int ttm_hosvd(const ttm_shape *shape, const void *X, void *A, void *B, void *C, 
     if (overlaps(ws, p.total, X, nx)) return TTM_ERR_ALIAS;
     hipStream_t st = static_cast<hipStream_t>(stream);
     unsigned char *w = static_cast<unsigned char *>(ws);
-    double *G = reinterpret_cast<double *>(w + p.off_G), *V = reinterpret_cast<double *>(w + p.off_V);
     double *part = reinterpret_cast<double *>(w + p.off_P);
+    JacobiArgs ja;
     int64_t eoff = 0;
     for (int n = 0; n < 3; ++n) {
+        double *G = reinterpret_cast<double *>(w + p.off_G[n]);
         if ((rc = gram_f64(s, static_cast<const double *>(X), n + 1, G, part, p.ks[n], st))) return rc;
-        double *ev = evals ? static_cast<double *>(evals) + eoff : nullptr;
-        rc = launch("ttm_sym_jacobi", st, [&] {
-            hipLaunchKernelGGL(k_sym_jacobi, dim3(1), dim3(EIG_THREADS), 0, st, G, int(s.I[n]), V, int(s.J[n]),
-                               static_cast<double *>(outs[n]), ev);
-        });
-        if (rc) return rc;
+        ja.G[n] = G;
+        ja.Vt[n] = reinterpret_cast<double *>(w + p.off_V[n]);
+        ja.U[n] = static_cast<double *>(outs[n]);
+        ja.evals[n] = evals ? static_cast<double *>(evals) + eoff : nullptr;
+        ja.n[n] = int(s.I[n]);
+        ja.J[n] = int(s.J[n]);
         eoff += s.I[n];
     }
-    return TTM_OK;
+    // the three eigensolves side by side, one workgroup each
+    return launch("ttm_sym_jacobi", st, [&] {
+        hipLaunchKernelGGL(k_sym_jacobi, dim3(3), dim3(EIG_THREADS), 0, st, ja);
+    });
 }
 
 }  // extern "C"
