@@ -432,6 +432,11 @@ def bench_hosvd(args, torch, ttm):
             "roofline": {"bound": "mfma", "achieved": round(tf, 2), "peak": 78.6, "unit": "TFLOP/s",
                          "frac": round(tf / 78.6, 4), "traffic": None, "kernel": "ttm_gram (FP64 Gram matrices)",
                          "kernel_ms": round(gram_ms, 4)},
+            # the step's time is the eigensolve: three workgroups (one per
+            # mode) of rotation rounds, each round a few LDS passes over the
+            # Gram matrix between barriers -- latency-bound, with no roofline
+            # of the chip's units to quote
+            "dominant_kernel": "ttm_sym_jacobi",
             "kernels_ms": {k: round(v[0] * v[1], 4) for k, v in kt.items()}}
 
 
