@@ -268,7 +268,8 @@ int ttm_batched_plan_config(const ttm_batched_plan *plan, int *out);
  * B_c the cyclic five-point right side), evaluated without forming D: the
  * right-hand side is built on the fly and the cyclic tridiagonal system
  * (Sec. 2.1) is solved in one of two ways.  Fibers of at least 2K points
- * (K = 40 for F64, 20 for F32) whose coefficient alpha makes rho^K below the
+ * and a multiple of 8 (K = 40 for F64, 24 for F32), whose coefficient alpha
+ * makes rho^K below the
  * rounding unit (rho = (1 - sqrt(1 - 4 alpha^2)) / (2 alpha); alpha = 1/3
  * gives 0.382) take a single pass: A_c factors as a product of two cyclic
  * first-order operators whose inverses are recursions that forget their

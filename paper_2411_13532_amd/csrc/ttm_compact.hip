@@ -2,11 +2,11 @@
 // Eq. (cfds), applied along one mode of a periodic 3-way field without forming
 // D = A_c^-1 B_c.  Two solvers of the cyclic tridiagonal system:
 //
-// Single pass (fibers of at least 2K points, K = 40 in float64, 20 in float32,
-// and |alpha| small enough that rho^K is below the rounding unit): the
-// circulant factorization of A_c below turns the solve into two first-order
-// recursions that forget their start after K points, so each point is read
-// once and written once (the algorithmic two transfers).
+// Single pass (fibers of at least 2K points and a multiple of 8, K = 40 in
+// float64, 24 in float32, and |alpha| small enough that rho^K is below the
+// rounding unit): the circulant factorization of A_c below turns the solve
+// into two first-order recursions that forget their start after K points, so
+// each point is read once and written once (the algorithmic two transfers).
 //
 // Exact sweeps (shorter fibers): the five-point right-hand side is built on
 // the fly and fused with the forward pass of a cyclic tridiagonal solve
@@ -412,7 +412,10 @@ struct OnePassArgs {
 // addresses at every step).  The forward recursion runs K + L points ahead of
 // the outputs in a register window F[K + L]; every L points the backward
 // recursion runs over the window from its far end and the first L values are
-// stored.  The stencil reads of a block are issued before its recursion.
+// stored.  The stencil reads of a block are issued before its recursion.  The
+// warm-up reads the K + 4 points before point 0 (cyclically); the window past
+// the fiber's end reuses f_0 .. f_{K-1} kept in registers, so a fiber is read
+// n + K + 8 times.
 template <typename T, int K, int L>
 __global__ void __launch_bounds__(256) k_compact_lines(const OnePassArgs a, const T *__restrict__ X,
                                                        T *__restrict__ Y) {
@@ -439,18 +442,44 @@ __global__ void __launch_bounds__(256) k_compact_lines(const OnePassArgs a, cons
             up1 = up2;
             return d;
         };
+        // the backward recursion over the window from its far end; the first
+        // L values are the outputs of points b .. b + L - 1; then the window
+        // moves on by L
+        auto emit = [&](T (&W)[K + L], int64_t b0) __attribute__((always_inline)) {
+            T g = T(0);
+#pragma unroll
+            for (int i = K + L - 1; i >= L; --i) g = W[i] - rho * g;
+            T out[L];
+#pragma unroll
+            for (int i = L - 1; i >= 0; --i) {
+                g = W[i] - rho * g;
+                out[i] = scale * g;
+            }
+#pragma unroll
+            for (int i = 0; i < L; ++i)
+                if (b0 + i < n) y[(b0 + i) * s] = out[i];
+#pragma unroll
+            for (int i = 0; i < K; ++i) W[i] = W[i + L];
+        };
         // forward warm-up over the K points before point 0
         T fprev = T(0);
 #pragma unroll 8
         for (int t = 0; t < K; ++t) fprev = step(u[next_index() * s]) - rho * fprev;
-        // F[i] = f_{b + i}: first f_0 .. f_{K-1}
-        T F[K + L];
+        // F[i] = f_{b + i}: first f_0 .. f_{K-1}, kept (fs) for the window
+        // past the fiber's end (f is cyclic: f_{n + i} = f_i), so the last
+        // blocks read nothing again
+        T F[K + L], fs[K];
 #pragma unroll
         for (int t = 0; t < K; ++t) {
             fprev = step(u[next_index() * s]) - rho * fprev;
             F[t] = fprev;
+            fs[t] = fprev;
         }
-        for (int64_t b = 0; b < n; b += L) {
+        // n and K are multiples of L (host): the last K / L blocks take the
+        // whole new part of their window from fs
+        static_assert(K % L == 0, "window blocks");
+        int64_t b = 0;
+        for (; b + K + L <= n; b += L) {
             T v[L];
 #pragma unroll
             for (int t = 0; t < L; ++t) v[t] = u[next_index() * s];
@@ -459,20 +488,13 @@ __global__ void __launch_bounds__(256) k_compact_lines(const OnePassArgs a, cons
                 fprev = step(v[t]) - rho * fprev;
                 F[K + t] = fprev;
             }
-            T g = T(0);
+            emit(F, b);
+        }
 #pragma unroll
-            for (int i = K + L - 1; i >= L; --i) g = F[i] - rho * g;
-            T out[L];
+        for (int m = 0; m < K / L; ++m, b += L) {
 #pragma unroll
-            for (int i = L - 1; i >= 0; --i) {
-                g = F[i] - rho * g;
-                out[i] = scale * g;
-            }
-#pragma unroll
-            for (int i = 0; i < L; ++i)
-                if (b + i < n) y[(b + i) * s] = out[i];
-#pragma unroll
-            for (int i = 0; i < K; ++i) F[i] = F[i + L];
+            for (int t = 0; t < L; ++t) F[K + t] = fs[m * L + t];
+            emit(F, b);
         }
     }
 }
@@ -649,11 +671,11 @@ int ttm_compact_apply(const int64_t *dims, int mode, const void *X, void *Y, int
     // single pass where the recursions' truncation is below the rounding unit
     // (coefficients for the exact sweeps are still prepared when asked, so a
     // later prepared call may take either path)
-    const int KT = dtype == TTM_F64 ? 40 : 20;
+    const int KT = dtype == TTM_F64 ? 40 : 24;
     const double alpha = coef->alpha;
     const double rho = alpha == 0.0 ? 0.0 : (1.0 - sqrt(1.0 - 4.0 * alpha * alpha)) / (2.0 * alpha);
     const double unit = dtype == TTM_F64 ? 0x1p-53 : 0x1p-24;
-    bool onepass = pow(fabs(rho), double(KT)) <= 0.5 * unit && n >= 2 * KT;
+    bool onepass = pow(fabs(rho), double(KT)) <= 0.5 * unit && n >= 2 * KT && n % 8 == 0;
     int lc = 0;
     if (mode == 3) {
         const int64_t VE = int64_t(16 / es);
@@ -722,16 +744,16 @@ int ttm_compact_apply(const int64_t *dims, int mode, const void *X, void *Y, int
                                        static_cast<float *>(Y));
                 };
                 switch (lc) {
-                    case 0: args(k_compact_rows1p<float, 20, 1>); break;
-                    case 1: args(k_compact_rows1p<float, 20, 2>); break;
-                    case 2: args(k_compact_rows1p<float, 20, 4>); break;
-                    case 3: args(k_compact_rows1p<float, 20, 8>); break;
-                    default: args(k_compact_rows1p<float, 20, 16>); break;
+                    case 0: args(k_compact_rows1p<float, 24, 1>); break;
+                    case 1: args(k_compact_rows1p<float, 24, 2>); break;
+                    case 2: args(k_compact_rows1p<float, 24, 4>); break;
+                    case 3: args(k_compact_rows1p<float, 24, 8>); break;
+                    default: args(k_compact_rows1p<float, 24, 16>); break;
                 }
             });
         else if (rc == TTM_OK && onepass)
             rc = launch("ttm_compact", st, [&] {
-                hipLaunchKernelGGL((k_compact_lines<float, 20, 8>), dim3(blocks), dim3(256), 0, st, oa,
+                hipLaunchKernelGGL((k_compact_lines<float, 24, 8>), dim3(blocks), dim3(256), 0, st, oa,
                                    static_cast<const float *>(X), static_cast<float *>(Y));
             });
         else if (rc == TTM_OK && mode == 3)

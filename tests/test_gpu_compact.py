@@ -47,10 +47,12 @@ def test_compact_matches_oracle(shape, dt):
 
 
 # fibers long enough for the single-pass sweep (at least twice the
-# recursion's truncation length: 80 points in float64, 40 in float32) on
-# every mode, including mode-3 rows of 64 c points (c = 1 .. 16) and the
-# shortest admissible fibers; the shorter fibers above take the exact sweeps
-ONEPASS_SHAPES = [(512, 4, 16), (4, 512, 16), (4, 16, 512), (80, 3, 5), (40, 6, 64), (8, 8, 1024), (3, 5, 128)]
+# recursion's truncation length, 80 points in float64 and 48 in float32, and
+# a multiple of 8) on every mode, including mode-3 rows of 64 c points
+# (c = 1 .. 16) and the shortest admissible fibers; the other fibers here and
+# above take the exact sweeps
+ONEPASS_SHAPES = [(512, 4, 16), (4, 512, 16), (4, 16, 512), (80, 3, 5), (48, 6, 64), (8, 8, 1024), (3, 5, 128),
+                  (84, 7, 9)]
 
 
 @pytest.mark.parametrize("dt", [torch.float64, torch.float32], ids=["f64", "f32"])
