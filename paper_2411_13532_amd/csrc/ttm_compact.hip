@@ -511,7 +511,8 @@ __global__ void __launch_bounds__(256) k_compact_lines(const OnePassArgs a, cons
 // Rows of n = 64 C points, C a power of two, n <= 256 VE (at most four
 // 16-byte words per lane); the recursions are unrolled.
 template <typename T, int K, int C>
-__global__ void __launch_bounds__(256) k_compact_rows1p(const OnePassArgs a, const T *__restrict__ X,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+k_compact_rows1p(const OnePassArgs a, const T *__restrict__ X,
                                                         T *__restrict__ Y) {
     constexpr int VE = 16 / int(sizeof(T)), WPL = 4;
     constexpr int lc = C == 1 ? 0 : C == 2 ? 1 : C == 4 ? 2 : C == 8 ? 3 : 4;
