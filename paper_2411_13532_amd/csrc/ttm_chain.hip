@@ -729,7 +729,7 @@ __global__ void __launch_bounds__(LC_THREADS, 1) k_slab_lc(const SlabArgs a) {
     // copies: 8 rows (or columns) of 128 bytes per instruction; lane l fills
     // word l % 8 of row l / 8 with logical word (l % 8) ^ ((row >> 1) & 7).
     // Addresses are a uniform base plus a 32-bit lane offset (the host
-    // guarantees 256 rows of X and the columns of C span less than 4 GiB);
+    // guarantees 256 rows of X, the columns of C and B each span less than 4 GiB);
     // X's lane offsets change only at a tile whose rows run past the range,
     // where rows are clamped to the last one.
     const int drow = lane >> 3, dpos = lane & 7;
@@ -836,26 +836,132 @@ __global__ void __launch_bounds__(LC_THREADS, 1) k_slab_lc(const SlabArgs a) {
             after_group(G);
         });
     };
-    auto tile_end = [&](int64_t t) __attribute__((always_inline)) {
+    // Mode-2 step of a tile with B staged through LDS.  The four column waves
+    // of a row half need the same B fragments; copied once per workgroup,
+    // B costs a quarter of the L2 reads of per-wave loads, and the copies of
+    // several phases are in flight at once.  A phase is one k-step of 32 rows
+    // in each half (the W pairs p) for JP 16-row blocks of j2: B[j2][32 rows]
+    // of both halves, hi (and lo), 64 bytes per j2 row with the 16-byte
+    // pieces XOR-swizzled by (j2 row >> 2) & 3.  The buffers are the X and C
+    // stages of the tile's last chunk, free once every wave has consumed
+    // them; NBUF - 1 phases are in flight ahead of the one being multiplied.
+    constexpr int PARTS = X3 ? 2 : 1;
+    constexpr int JP = JB < 4 ? JB : 4;                  // j2 blocks per phase
+    constexpr bool LDS_B = PARTS * JP >= 4;              // whole copy instructions per wave
+    constexpr int PB = PARTS * JP * 2048;                // bytes per phase
+    constexpr int XB = LC_XSTAGE / PB, CB = CSTAGE / PB; // phase buffers in an X / a C stage
+    constexpr int NBUF = XB + CB < 4 ? XB + CB : 4;
+    constexpr int NJH = JB / JP, NPH = (MB / 2) * NJH;
+    constexpr int CPB = LDS_B ? PARTS * 2 * JP / 8 : 1;  // copy instructions per wave and phase
+    static_assert(!LDS_B || (NBUF >= 2 && XB * PB == LC_XSTAGE && CB >= 1 && 8 * CPB == PARTS * 2 * JP),
+                  "mode-2 phase buffers");
+    // copy instruction k of this wave fills phase rows 16 i .. 16 i + 15 with
+    // i = wave + 8 k: part i / (2 JP), half (i / JP) % 2, j2 rows (i % JP) * 16 +
+    // lane / 4; lane l loads logical piece (l % 4) ^ ((row >> 2) & 3)
+    uint32_t bofs[CPB];
+    {
+        const int r = lane >> 2, piece = (lane & 3) ^ ((r >> 2) & 3);
+#pragma unroll
+        for (int k = 0; k < CPB; ++k) {
+            const int i = wave + 8 * k;
+            bofs[k] = uint32_t((jbase * 16 + (i % JP) * 16 + r) * a.ldb * 2 + piece * 16);
+        }
+    }
+    // per-lane LDS offset of the B fragment words: row wr * JP * 16 + l16
+    const uint32_t brd = uint32_t((wr * JP * 16 + l16) * 64 + ((g ^ ((l16 >> 2) & 3)) << 4));
+    auto mode2_lds = [&](int64_t t, bool live, uint32_t xs_done, uint32_t cs_done) __attribute__((always_inline)) {
+        constexpr int PAIRS = MB / 2;
+        u32x4 wh[PAIRS][NBW], wl[PAIRS][NBW];
+#pragma unroll
+        for (int p = 0; p < PAIRS; ++p)
+#pragma unroll
+            for (int nb = 0; nb < NBW; ++nb) {
+                const float v[8] = {wacc[2 * p][nb][0], wacc[2 * p][nb][1], wacc[2 * p][nb][2], wacc[2 * p][nb][3],
+                                    wacc[2 * p + 1][nb][0], wacc[2 * p + 1][nb][1], wacc[2 * p + 1][nb][2],
+                                    wacc[2 * p + 1][nb][3]};
+                if constexpr (X3) bf16_split8(v, wh[p][nb], &wl[p][nb]);
+                else wh[p][nb] = bf16_round8(v);
+            }
+        // byte column of each half's rows in B; a half past the range copies
+        // (and ignores) columns 0..127, which exist in every row of B
+        const int64_t hb = row_begin + t * LC_TM;
+        const uint32_t colb[2] = {uint32_t(hb * 2), hb + RW < row_end ? uint32_t((hb + RW) * 2) : 0u};
+        const char *bsrc[2] = {static_cast<const char *>(a.Bhi), static_cast<const char *>(X3 ? a.Blo : a.Bhi)};
+        auto buf = [&](int b) __attribute__((always_inline)) -> uint32_t {
+            return b < XB ? xs_done + uint32_t(b * PB) : cs_done + uint32_t((b - XB) * PB);
+        };
+        auto issue = [&](auto PH) __attribute__((always_inline)) {
+            constexpr int ph = decltype(PH)::value, p = ph / NJH, jh = ph % NJH;
+            const uint32_t dst = buf(ph % NBUF);
+#pragma unroll
+            for (int k = 0; k < CPB; ++k) {
+                const int i = wave + 8 * k;
+                const char *src = bsrc[i / (2 * JP)] + colb[(i / JP) & 1] + int64_t(jh * JP * 16) * a.ldb * 2 + 64 * p;
+                dma16_to_lds_m0(src + bofs[k], dst + uint32_t(i * 1024));
+            }
+        };
+        // every wave has consumed the chunk's X and C stages
+        __builtin_amdgcn_s_barrier();
+        static_for<NBUF - 1>([&](auto I) __attribute__((always_inline)) {
+            if constexpr (decltype(I)::value < NPH) issue(I);
+        });
+        static_for<NPH>([&](auto PH) __attribute__((always_inline)) {
+            constexpr int ph = decltype(PH)::value, p = ph / NJH, jh = ph % NJH;
+            constexpr int last = ph + NBUF - 2 < NPH - 1 ? ph + NBUF - 2 : NPH - 1;
+            // this wave's copies of phase ph (and of everything issued
+            // before them) have landed; after the barrier, every wave's have,
+            // and every wave is done with phase ph - 1's buffer
+            wait_vmcnt<CPB * (last - ph)>();
+            __builtin_amdgcn_s_barrier();
+            if constexpr (ph + NBUF - 1 < NPH) issue(std::integral_constant<int, ph + NBUF - 1>{});
+            if (live) {
+                const uint32_t ba = buf(ph % NBUF) + brd;
+                u32x4 fr[JP][PARTS];
+                static_for<JP * PARTS>([&](auto R) __attribute__((always_inline)) {
+                    constexpr int rr = decltype(R)::value, jj = rr / PARTS, part = rr % PARTS;
+                    fr[jj][part] = lds_read16_at<part * JP * 2048 + jj * 1024>(ba);
+                });
+                static_for<JP>([&](auto JJ) __attribute__((always_inline)) {
+                    constexpr int jj = decltype(JJ)::value;
+                    lds_wait<(JP - 1 - jj) * PARTS>();
+                    lds_dep(fr[jj][0]);
+                    if constexpr (X3) lds_dep(fr[jj][PARTS - 1]);
+#pragma unroll
+                    for (int nb = 0; nb < NBW; ++nb) {
+                        auto &acc = vacc[jh * JP + jj][nb];
+                        acc = mfma_bf16(fr[jj][0], wh[p][nb], acc);
+                        if constexpr (X3) {
+                            acc = mfma_bf16(fr[jj][0], wl[p][nb], acc);
+                            acc = mfma_bf16(fr[jj][PARTS - 1], wh[p][nb], acc);
+                        }
+                    }
+                });
+            }
+        });
+    };
+    auto tile_end = [&](int64_t t, uint32_t xs_done, uint32_t cs_done) __attribute__((always_inline)) {
         const int64_t wrow0 = row_begin + t * LC_TM + wr * RW;
         // a row half that starts past the range (the upper half of a partial
         // last tile) contributes nothing and reads no B: its columns could lie
         // past the padded row stride of B, which is a multiple of 128 only
-        if (wrow0 < row_end) {
-            if (wrow0 + RW > row_end) {
+        const bool live = wrow0 < row_end;
+        if (live && wrow0 + RW > row_end) {
 #pragma unroll
-                for (int mb = 0; mb < MB; ++mb)
+            for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const bool dead = wrow0 + mb * 16 + TR::acc_row(g, r) >= row_end;
+                for (int r = 0; r < 4; ++r) {
+                    const bool dead = wrow0 + mb * 16 + TR::acc_row(g, r) >= row_end;
 #pragma unroll
-                        for (int nb = 0; nb < NBW; ++nb)
-                            if (dead) wacc[mb][nb][r] = 0.f;
-                    }
-            }
-            // rows past the range in this half contribute zeros; B's padded
-            // columns up to the next multiple of 128 are zeros
-            slab_mode2_pipe<MATH, MB, NBW, JB>(vacc, wacc, a, jbase, wrow0, l16, g);
+                    for (int nb = 0; nb < NBW; ++nb)
+                        if (dead) wacc[mb][nb][r] = 0.f;
+                }
+        }
+        // rows past the range in this half contribute zeros; B's padded
+        // columns up to the next multiple of 128 are zeros
+        if constexpr (LDS_B) {
+            mode2_lds(t, live, xs_done, cs_done);
+        } else {
+            if (live) slab_mode2_pipe<MATH, MB, NBW, JB>(vacc, wacc, a, jbase, wrow0, l16, g);
         }
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
@@ -911,7 +1017,7 @@ __global__ void __launch_bounds__(LC_THREADS, 1) k_slab_lc(const SlabArgs a) {
                 if (x_next) dma16_to_lds_m0(xb + xlo[g / 2], xstage + uint32_t((wave * XOPS + g / 2) * 1024));
         });
         if (last_of_tile) {
-            tile_end(t);
+            tile_end(t, xs, cs);
             kc = 0;
             ++t;
         } else {
@@ -1385,6 +1491,7 @@ static int dma_rowbytes(const SlabArgs &a) {
     if (mode == 0 || mode == 3) {                            // C through LDS where it applies
         if constexpr (WC == 4 && (MATH == M_BF16 || MATH == M_BF16X3) && std::is_same<XT, uint16_t>::value)
             if (a.I3 % 64 == 0 && a.ldc % 64 == 0 && a.I3 <= (int64_t(1) << 22) && a.ldc <= (int64_t(1) << 22) &&
+                a.J2pad * a.ldb < (int64_t(1) << 31) &&
                 aligned(a.Chi, 16) && (!a.Clo || aligned(a.Clo, 16)) &&
                 (mode == 3 || a.rows_per_split >= LC_TM))
                 return 128;
