@@ -729,7 +729,7 @@ __global__ void __launch_bounds__(LC_THREADS, 1) k_slab_lc(const SlabArgs a) {
     // copies: 8 rows (or columns) of 128 bytes per instruction; lane l fills
     // word l % 8 of row l / 8 with logical word (l % 8) ^ ((row >> 1) & 7).
     // Addresses are a uniform base plus a 32-bit lane offset (the host
-    // guarantees 256 rows of X, the columns of C and B each span less than 4 GiB);
+    // guarantees 256 rows of X, the columns of C and B each span less than 2 GiB);
     // X's lane offsets change only at a tile whose rows run past the range,
     // where rows are clamped to the last one.
     const int drow = lane >> 3, dpos = lane & 7;
@@ -760,7 +760,7 @@ __global__ void __launch_bounds__(LC_THREADS, 1) k_slab_lc(const SlabArgs a) {
     auto copy_x = [&](uint32_t stage, int64_t t, int kc) __attribute__((always_inline)) {
         const char *base = xslab + (row_begin + t * LC_TM) * xrow_bytes + kc * 128;
 #pragma unroll
-        for (int j = 0; j < XOPS; ++j) dma16_to_lds_m0(base + xlo[j], stage + uint32_t((wave * XOPS + j) * 8 * 128));
+        for (int j = 0; j < XOPS; ++j) dma16s_to_lds_m0(base, xlo[j], stage + uint32_t((wave * XOPS + j) * 8 * 128));
     };
     auto copy_c = [&](uint32_t stage, int kc) __attribute__((always_inline)) {
 #pragma unroll
@@ -768,7 +768,7 @@ __global__ void __launch_bounds__(LC_THREADS, 1) k_slab_lc(const SlabArgs a) {
             const int idx = wave * COPS + j;
             const int part = idx / (COLS / 8);         // 0: hi, 1: lo
             const int col0 = (idx % (COLS / 8)) * 8;
-            dma16_to_lds_m0(cbase[part] + kc * 128 + clo[j], stage + uint32_t(part * CPART + col0 * 128));
+            dma16s_to_lds_m0(cbase[part] + kc * 128, clo[j], stage + uint32_t(part * CPART + col0 * 128));
         }
     };
 
@@ -897,7 +897,7 @@ __global__ void __launch_bounds__(LC_THREADS, 1) k_slab_lc(const SlabArgs a) {
             for (int k = 0; k < CPB; ++k) {
                 const int i = wave + 8 * k;
                 const char *src = bsrc[i / (2 * JP)] + colb[(i / JP) & 1] + int64_t(jh * JP * 16) * a.ldb * 2 + 64 * p;
-                dma16_to_lds_m0(src + bofs[k], dst + uint32_t(i * 1024));
+                dma16s_to_lds_m0(src, bofs[k], dst + uint32_t(i * 1024));
             }
         };
         // every wave has consumed the chunk's X and C stages
@@ -1014,7 +1014,7 @@ __global__ void __launch_bounds__(LC_THREADS, 1) k_slab_lc(const SlabArgs a) {
         compute(xs, cs, [&](auto G) __attribute__((always_inline)) {
             constexpr int g = decltype(G)::value;
             if constexpr (g % 2 == 1 && g / 2 < XOPS)
-                if (x_next) dma16_to_lds_m0(xb + xlo[g / 2], xstage + uint32_t((wave * XOPS + g / 2) * 1024));
+                if (x_next) dma16s_to_lds_m0(xb, xlo[g / 2], xstage + uint32_t((wave * XOPS + g / 2) * 1024));
         });
         if (last_of_tile) {
             tile_end(t, xs, cs);
@@ -1491,7 +1491,7 @@ static int dma_rowbytes(const SlabArgs &a) {
     if (mode == 0 || mode == 3) {                            // C through LDS where it applies
         if constexpr (WC == 4 && (MATH == M_BF16 || MATH == M_BF16X3) && std::is_same<XT, uint16_t>::value)
             if (a.I3 % 64 == 0 && a.ldc % 64 == 0 && a.I3 <= (int64_t(1) << 22) && a.ldc <= (int64_t(1) << 22) &&
-                a.J2pad * a.ldb < (int64_t(1) << 31) &&
+                a.J2pad * a.ldb < (int64_t(1) << 30) &&
                 aligned(a.Chi, 16) && (!a.Clo || aligned(a.Clo, 16)) &&
                 (mode == 3 || a.rows_per_split >= LC_TM))
                 return 128;

@@ -171,6 +171,12 @@ __device__ __forceinline__ uint32_t lds_offset(const void *p) {
 __device__ __forceinline__ void dma16_to_lds_m0(const void *g, uint32_t lds_addr) {
     asm volatile("s_nop 0\n\tglobal_load_lds_dwordx4 %0, off" : : "v"(g), "{m0}"(lds_addr) : "memory");
 }
+// The same with a wave-uniform base in SGPRs and a 32-bit per-lane byte
+// offset (below 2^31): the lane's address is sbase + voff, formed by the
+// memory unit, so the lane holds one register instead of a 64-bit address.
+__device__ __forceinline__ void dma16s_to_lds_m0(const void *sbase, uint32_t voff, uint32_t lds_addr) {
+    asm volatile("s_nop 0\n\tglobal_load_lds_dwordx4 %0, %1" : : "v"(voff), "s"(sbase), "{m0}"(lds_addr) : "memory");
+}
 // The same for 4 bytes per lane (LDS byte address m0 + 4 lane).
 __device__ __forceinline__ void dma4_to_lds_m0(const void *g, uint32_t lds_addr) {
     asm volatile("s_nop 0\n\tglobal_load_lds_dword %0, off" : : "v"(g), "{m0}"(lds_addr) : "memory");
