@@ -1593,20 +1593,35 @@ static int run_chain(const ChainPlan &p, const ttm_shape &s, const void *X, cons
         pa.perm32[f] = (f == 1 && (MATH == M_BF16 || MATH == M_BF16X3)) ? 1 : 0;
         maxn = std::max<int64_t>(maxn, Jpad[f] * ld[f]);
     }
+    // float and double operands whose padded arrays would equal the factors
+    // (rows a multiple of the tile, row length a multiple of the k chunk) are
+    // read where they are: the preparation would be a plain copy
+    bool direct = false;
+    if constexpr (MATH == M_F32 || MATH == M_F64) {
+        direct = true;
+        for (int f = 0; f < 3; ++f)
+            direct = direct && Jpad[f] == s.J[f] && ld[f] == s.I[f] && aligned(src[f], 16);
+    }
+    const void *fac[3];
+    for (int f = 0; f < 3; ++f) fac[f] = direct ? src[f] : static_cast<const void *>(ws + offh[f]);
     dim3 pgrid(unsigned(std::min<int64_t>(ceil_div(maxn, 256), 4096)), 3);
-    int rc;
-    if constexpr (MATH == M_F64)
-        rc = launch("ttm_prep", st, [&] { hipLaunchKernelGGL((k_prep_factors<double, MATH>), pgrid, dim3(256), 0, st, pa); });
-    else
-        rc = launch("ttm_prep", st, [&] { hipLaunchKernelGGL((k_prep_factors<float, MATH>), pgrid, dim3(256), 0, st, pa); });
+    int rc = TTM_OK;
+    if (!direct) {
+        if constexpr (MATH == M_F64)
+            rc = launch("ttm_prep", st,
+                        [&] { hipLaunchKernelGGL((k_prep_factors<double, MATH>), pgrid, dim3(256), 0, st, pa); });
+        else
+            rc = launch("ttm_prep", st,
+                        [&] { hipLaunchKernelGGL((k_prep_factors<float, MATH>), pgrid, dim3(256), 0, st, pa); });
+    }
     if (rc) return rc;
 
     // 2. slab kernel (modes 3 and 2)
     SlabArgs sa;
     sa.X = X;
     sa.I1 = s.I[0]; sa.I2 = s.I[1]; sa.I3 = s.I[2];
-    sa.Chi = ws + p.off_Chi; sa.Clo = p.split ? ws + p.off_Clo : nullptr; sa.ldc = p.ldc;
-    sa.Bhi = ws + p.off_Bhi; sa.Blo = p.split ? ws + p.off_Blo : nullptr; sa.ldb = p.ldb;
+    sa.Chi = fac[2]; sa.Clo = p.split ? ws + p.off_Clo : nullptr; sa.ldc = p.ldc;
+    sa.Bhi = fac[1]; sa.Blo = p.split ? ws + p.off_Blo : nullptr; sa.ldb = p.ldb;
     sa.V = ws + p.off_V;
     sa.J2pad = p.J2pad; sa.J3pad = p.J3pad;
     sa.P = p.P; sa.S = p.S;
@@ -1627,7 +1642,7 @@ static int run_chain(const ChainPlan &p, const ttm_shape &s, const void *X, cons
 
     // 3. mode 1
     Mode1Args ma;
-    ma.Ahi = ws + p.off_Ahi; ma.Alo = p.split ? ws + p.off_Alo : nullptr; ma.lda = p.lda;
+    ma.Ahi = fac[0]; ma.Alo = p.split ? ws + p.off_Alo : nullptr; ma.lda = p.lda;
     ma.V = ws + p.off_V; ma.I1 = s.I[0]; ma.P = p.P;
     ma.NN = p.J2pad * p.J3pad; ma.J3pad = p.J3pad;
     ma.Y = Y; ma.Ypart = p.KS > 1 ? ws + p.off_Yp : nullptr;

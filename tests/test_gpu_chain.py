@@ -65,7 +65,9 @@ FORMS = [("f64", None), ("f32", None), ("f32", torch.bfloat16), ("bf16", torch.b
 FORM_IDS = [f"{m}-x{'bf16' if x is torch.bfloat16 else 'native'}" for m, x in FORMS]
 
 # shapes spanning several row tiles and k chunks with ragged tails, the
-# unaligned (scalar-load) path, wide J (column and j2 tiling), and size-1 modes
+# unaligned (scalar-load) path, wide J (column and j2 tiling), size-1 modes,
+# and (last) factors whose shapes need no padding, read in place by the
+# float and double forms
 SHAPES = [
     ((37, 150, 200), (20, 35, 70)),
     ((3, 260, 136), (130, 140, 150)),
@@ -74,6 +76,7 @@ SHAPES = [
     ((1, 1, 1), (1, 1, 1)),
     ((4, 5, 6), (7, 8, 9)),
     ((16, 300, 24), (2, 260, 16)),
+    ((64, 128, 96), (16, 32, 32)),
 ]
 
 
@@ -250,8 +253,12 @@ def test_c3_full_size(c3_inputs, math):
 # The automatic selection on bf16 X with ragged multi-tile row ranges: several
 # 256-row tiles per workgroup with a partial last tile, 384-row ranges over
 # two splits, and one or two 64-value chunks per row (the short-row preamble).
+# The last three cover the mode-2 step's B staging with one column block per
+# wave and eight j2 blocks (three phase buffers in bf16x3), two j2 blocks
+# with two column blocks, and a single j2 block (B fragments from L2).
 # ---------------------------------------------------------------------------
-LC_SHAPES = [((1024, 300, 64), (24, 40, 100)), ((512, 600, 128), (33, 40, 70)), ((1024, 600, 64), (16, 20, 48))]
+LC_SHAPES = [((1024, 300, 64), (24, 40, 100)), ((512, 600, 128), (33, 40, 70)), ((1024, 600, 64), (16, 20, 48)),
+             ((512, 300, 128), (10, 120, 50)), ((512, 280, 64), (10, 30, 80)), ((512, 300, 128), (5, 16, 100))]
 
 
 @pytest.mark.parametrize("form", FORMS, ids=FORM_IDS)
