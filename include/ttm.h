@@ -253,8 +253,19 @@ int ttm_batched_autotune(ttm_batched_plan *plan, const void *X, const void *A,
 /* The plan's current launch shape (out holds 4 ints): out[0] = threads per
  * block, out[1] = resident blocks per compute unit, out[2] = total blocks,
  * out[3] = kernel variant (float: 0 keeps the next cuboid's inputs in
- * registers at two waves per SIMD, 1 runs three waves per SIMD without). */
+ * registers at two waves per SIMD, 1 and 2 run three and four waves per
+ * SIMD without; double: every variant runs the same kernel). */
 int ttm_batched_plan_config(const ttm_batched_plan *plan, int *out);
+
+/* Pins the plan's launch shape, as the autotuner does with its choice:
+ * threads per block (64, 128 or 256), resident blocks per compute unit (at
+ * least 1 and at most what LDS and the variant's registers allow) and the
+ * variant (0, 1 or 2, as in ttm_batched_plan_config).  Rebuilds the
+ * assignment of cuboids to waves (synchronising `stream`); the results of
+ * every shape are identical.  TTM_ERR_INVALID_ARG for a shape outside these
+ * ranges, TTM_ERR_HIP. */
+int ttm_batched_plan_set_config(ttm_batched_plan *plan, int threads, int blocks_per_cu, int variant,
+                                void *stream);
 
 /*
  * The compact sixth-order first derivative of Sec. 4.2, Eq. (cfds), on a

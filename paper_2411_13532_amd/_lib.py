@@ -59,6 +59,7 @@ SIGNATURES = {
     "ttm_chain_batched_loop": (INT, [P, P, P, P, P, P, P]),
     "ttm_batched_autotune": (INT, [P, P, P, P, P, P, P, INT, ctypes.POINTER(ctypes.c_double)]),
     "ttm_batched_plan_config": (INT, [P, P]),
+    "ttm_batched_plan_set_config": (INT, [P, INT, INT, INT, P]),
     "ttm_stream_copy": (INT, [P, P, SZ, P]),
     "ttm_reorder": (INT, [P, P, P, P, INT, INT, P]),
     "ttm_hosvd_workspace_size": (SZ, [PShape]),

@@ -12,8 +12,10 @@
 //   mode 2: fibers (i1, j3) of W along i2     -> V[i1][j2][j3]
 //   mode 1: fibers (j2, j3) of V along i1     -> Y[j1][j2][j3]
 // One LDS region per wave holds X, then W, then V (each pass reads all its
-// fibers into registers before the region is overwritten), so a wave needs
-// the three factors plus one n^3 region: at n <= 13 about 11 KiB.  X is read
+// fibers into registers before the region is overwritten), and one factor
+// region holds the factor of the current mode (the cuboid's three factors
+// wait in registers, at most four elements per lane each): at n <= 13 about
+// 9.6 KiB per wave, so that four waves per SIMD fit in LDS.  X is read
 // from HBM with coalesced loads of the whole cuboid and scattered to fibers
 // at odd strides (no bank conflicts); Y is written with coalesced stores.
 // The next cuboid's X and factors are loaded into registers while the wave
@@ -65,7 +67,9 @@ constexpr int BATCH_PF = 16;
 __device__ __forceinline__ int row_of(int e, float inv_len) { return int((float(e) + 0.5f) * inv_len); }
 
 // n (<= 256) elements of a factor (rows of len), already loaded as
-// r[u] = element u * 64 + lane, into LDS rows of stride P.
+// r[u] = element u * 64 + lane, into LDS rows of stride P, and zeros into the
+// P - len (< 4) padding columns of its n / len rows (the dot products read
+// them against zero fiber values: they must be finite).
 template <typename T>
 __device__ __forceinline__ void factor_regs_to_lds(const T (&r)[4], int n, int len, int P, T *dst, int lane) {
     const float inv = __builtin_amdgcn_rcpf(float(len));
@@ -74,6 +78,11 @@ __device__ __forceinline__ void factor_regs_to_lds(const T (&r)[4], int n, int l
         const int e = u * 64 + lane;
         const int row = row_of(e, inv);
         if (e < n) dst[row * P + (e - row * len)] = r[u];
+    }
+    const int pad = P - len, rows = n / len;
+    if (pad > 0 && lane < rows * pad) {
+        const int row = lane / pad;
+        dst[row * P + len + (lane - row * pad)] = T(0);
     }
 }
 
@@ -193,8 +202,9 @@ k_batched(const BatchArgs a, const T *__restrict__ X, const T *__restrict__ Ag, 
     }
 
     // the first PF rows of 64 elements of a cuboid's X and its three factors
-    // (at most 256 elements each, 4 per lane)
-    T pre[PF > 0 ? PF : 1], pf[3][PFF];
+    // (at most 256 elements each, 4 per lane); fr: the current cuboid's
+    // factors until their modes
+    T pre[PF > 0 ? PF : 1], pf[3][PFF], fr[3][4];
     auto load_inputs = [&](const CuboidDesc &d) __attribute__((always_inline)) {
         const int nx = d.d[0] * d.d[1] * d.d[2];
         const T *xs = X + d.ox;
@@ -228,34 +238,29 @@ k_batched(const BatchArgs a, const T *__restrict__ X, const T *__restrict__ Ag, 
         const int I1 = d.d[0], I2 = d.d[1], I3 = d.d[2], J1 = d.d[3], J2 = d.d[4], J3 = d.d[5];
         // factor rows padded to multiples of 4 (zeros); odd strides for fibers
         const int P1 = (I1 + 3) & ~3, P2 = (I2 + 3) & ~3, P3 = (I3 + 3) & ~3;
-        T *As = fac, *Bs = fac + J1 * P1, *Cs = Bs + J2 * P2;
         const int nx = I1 * I2 * I3;
 
-        // stage 0: factors into zero-padded LDS rows, X (prefetched, plus any
+        // stage 0: the factors into registers (prefetched, or loaded now),
+        // C into the zero-padded LDS factor rows, X (prefetched, plus any
         // rest) into fibers of odd stride SX
-        {
-            const int nfac = J1 * P1 + J2 * P2 + J3 * P3;
-            for (int e = lane; e < nfac; e += 64) fac[e] = T(0);
-        }
-        wave_sync();
         if constexpr (PF > 0) {
-            factor_regs_to_lds(pf[0], J1 * I1, I1, P1, As, lane);
-            factor_regs_to_lds(pf[1], J2 * I2, I2, P2, Bs, lane);
-            factor_regs_to_lds(pf[2], J3 * I3, I3, P3, Cs, lane);
+#pragma unroll
+            for (int f = 0; f < 3; ++f)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) fr[f][u] = pf[f][u];
         } else {
             const T *fs[3] = {Ag + d.oa, Bg + d.ob, Cg + d.oc};
-            T *fd[3] = {As, Bs, Cs};
-            const int len[3] = {I1, I2, I3}, Pn[3] = {P1, P2, P3};
 #pragma unroll
             for (int f = 0; f < 3; ++f) {
                 const int n = d.d[3 + f] * d.d[f];
-                const float inv = __builtin_amdgcn_rcpf(float(len[f]));
-                for (int e = lane; e < n; e += 64) {
-                    const int row = row_of(e, inv);
-                    fd[f][row * Pn[f] + (e - row * len[f])] = fs[f][e];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int e = u * 64 + lane;
+                    if (u * 64 < n) fr[f][u] = fs[f][e < n ? e : n - 1];   // uniform: rows of 64 the factor fills
                 }
             }
         }
+        factor_regs_to_lds(fr[2], J3 * I3, I3, P3, fac, lane);
         const int SX = I3 | 1;
         const float inv3 = __builtin_amdgcn_rcpf(float(I3));
 #pragma unroll
@@ -285,20 +290,24 @@ k_batched(const BatchArgs a, const T *__restrict__ X, const T *__restrict__ Ag, 
 
         // mode 3: fiber f = (i1, i2) along i3 -> W[f][j3] at row stride SW
         const int SW = J3 | 1;
-        mode_any(buf, I1 * I2, I3, Cs, P3, J3, [&](int f) { return f * SX; }, 1, buf, static_cast<T *>(nullptr),
+        mode_any(buf, I1 * I2, I3, fac, P3, J3, [&](int f) { return f * SX; }, 1, buf, static_cast<T *>(nullptr),
                  [&](int f) { return f * SW; }, 1, lane);
+        wave_sync();
+        factor_regs_to_lds(fr[1], J2 * I2, I2, P2, fac, lane);
         wave_sync();
         // mode 2: fiber g = (i1, j3) along i2 -> V[i1][j2][j3] at i1 stride SV
         const int SV = (J2 * J3) | 1;
         const float invJ3 = __builtin_amdgcn_rcpf(float(J3));
-        mode_any(buf, I1 * J3, I2, Bs, P2, J2,
+        mode_any(buf, I1 * J3, I2, fac, P2, J2,
                  [&](int g) { const int i1 = row_of(g, invJ3); return i1 * I2 * SW + (g - i1 * J3); }, SW, buf,
                  static_cast<T *>(nullptr), [&](int g) { const int i1 = row_of(g, invJ3); return i1 * SV + (g - i1 * J3); },
                  J3, lane);
         wave_sync();
+        factor_regs_to_lds(fr[0], J1 * I1, I1, P1, fac, lane);
+        wave_sync();
         // mode 1: fiber h = (j2, j3) along i1 -> Y[j1][h]
         const int H = J2 * J3;
-        mode_any(buf, H, I1, As, P1, J1, [&](int h) { return h; }, SV, buf, Y + d.oy, [&](int h) { return h; }, H,
+        mode_any(buf, H, I1, fac, P1, J1, [&](int h) { return h; }, SV, buf, Y + d.oy, [&](int h) { return h; }, H,
                  lane);
         wave_sync();
     }
@@ -340,7 +349,7 @@ size_t lds_per_wave(const ttm_batched_plan *p) { return size_t(p->fac_elems + p-
 
 // resident waves per SIMD the register budget of a launch variant allows
 int variant_occupancy(int dtype, int variant) {
-    return dtype == TTM_F64 ? 1 : (variant == 0 ? 2 : 3);
+    return dtype == TTM_F64 ? 1 : variant + 2;
 }
 
 int max_blocks_per_cu(const ttm_batched_plan *p, int threads, int variant) {
@@ -406,14 +415,15 @@ BatchArgs make_args(const ttm_batched_plan *p) {
 }
 
 // Launch variants: the register budget of k_batched (resident waves per
-// SIMD).  float: 2 (with register prefetch of the next cuboid) or 3;
-// double: 1 for both.
-constexpr int BATCH_VARIANTS = 2;
+// SIMD).  float: 2 (with register prefetch of the next cuboid), 3 or 4;
+// double: 1 for all.
+constexpr int BATCH_VARIANTS = 3;
 const void *kernel_ptr(int dtype, int variant) {
     if (dtype == TTM_F64)
         return reinterpret_cast<const void *>(&k_batched<double, 1>);
     return variant == 0 ? reinterpret_cast<const void *>(&k_batched<float, 2>)
-                        : reinterpret_cast<const void *>(&k_batched<float, 3>);
+         : variant == 1 ? reinterpret_cast<const void *>(&k_batched<float, 3>)
+                        : reinterpret_cast<const void *>(&k_batched<float, 4>);
 }
 template <typename T>
 void launch_variant(int variant, dim3 grid, dim3 block, size_t lds, hipStream_t st, const BatchArgs &a, const void *X,
@@ -423,7 +433,8 @@ void launch_variant(int variant, dim3 grid, dim3 block, size_t lds, hipStream_t 
     T *y = static_cast<T *>(Y);
     constexpr bool F = std::is_same<T, float>::value;
     if (variant == 0 || !F) hipLaunchKernelGGL((k_batched<T, F ? 2 : 1>), grid, block, lds, st, a, x, pa, pb, pc, y);
-    else hipLaunchKernelGGL((k_batched<T, F ? 3 : 1>), grid, block, lds, st, a, x, pa, pb, pc, y);
+    else if (variant == 1) hipLaunchKernelGGL((k_batched<T, F ? 3 : 1>), grid, block, lds, st, a, x, pa, pb, pc, y);
+    else hipLaunchKernelGGL((k_batched<T, F ? 4 : 1>), grid, block, lds, st, a, x, pa, pb, pc, y);
 }
 
 // One launch of the persistent kernel with the plan's current assignment
@@ -557,8 +568,8 @@ int ttm_batched_plan_create(int64_t count, const int64_t *dims_host, int dtype, 
         auto ps = [](int64_t v) { return double(ceil_div(v, 64)); };
         p->cost[size_t(k)] = ps(d[0] * d[1]) * g4(d[2]) * g4(d[5]) + ps(d[0] * d[5]) * g4(d[1]) * g4(d[4]) +
                              ps(d[4] * d[5]) * g4(d[0]) * g4(d[3]) + double(ceil_div(d[0] * d[1] * d[2], 64));
-        p->fac_elems = std::max<int>(p->fac_elems, int(d[3] * round_up(d[0], 4) + d[4] * round_up(d[1], 4) +
-                                                       d[5] * round_up(d[2], 4)));
+        p->fac_elems = std::max<int>(p->fac_elems, int(std::max({d[3] * round_up(d[0], 4), d[4] * round_up(d[1], 4),
+                                                                  d[5] * round_up(d[2], 4)})));
         p->buf_elems = std::max<int>(p->buf_elems, int(std::max({d[0] * d[1] * (d[2] | 1), d[0] * d[1] * (d[5] | 1),
                                                                   d[0] * ((d[4] * d[5]) | 1)})));
     }
@@ -605,7 +616,7 @@ int ttm_batched_plan_create(int64_t count, const int64_t *dims_host, int dtype, 
     for (int64_t k = 0; k < count * 6; ++k) maxd = std::max(maxd, dims_host[k]);
     for (int64_t k = 0; k < count; ++k) sumc += p->cost[size_t(k)];
     char key[256];
-    snprintf(key, sizeof key, "%s|%s|v2|maxn%lld|count%lld|cost%lld", arch_name().c_str(),
+    snprintf(key, sizeof key, "%s|%s|v3|maxn%lld|count%lld|cost%lld", arch_name().c_str(),
              dtype == TTM_F64 ? "f64" : "f32", (long long)maxd, (long long)count, (long long)(sumc / count * 100));
     p->tune_key = key;
     if (tune_cache) {
@@ -644,6 +655,23 @@ int ttm_batched_plan_config(const ttm_batched_plan *p, int *out) {
     out[1] = p->blocks_per_cu;
     out[2] = int(p->assigned_waves / (p->threads / 64));
     out[3] = p->variant;
+    return TTM_OK;
+}
+
+int ttm_batched_plan_set_config(ttm_batched_plan *p, int threads, int blocks_per_cu, int variant, void *stream) {
+    if (!p || (threads != 64 && threads != 128 && threads != 256) || variant < 0 || variant >= BATCH_VARIANTS ||
+        blocks_per_cu < 1 || blocks_per_cu > max_blocks_per_cu(p, threads, variant))
+        return TTM_ERR_INVALID_ARG;
+    if (int rc = assign_waves(p, launch_waves(p, threads, blocks_per_cu), static_cast<hipStream_t>(stream))) return rc;
+    p->threads = threads;
+    p->blocks_per_cu = blocks_per_cu;
+    p->variant = variant;
+    if (p->exec) {   // the graph node keeps the old shape: rebuild on next use
+        (void)hipGraphExecDestroy(p->exec);
+        (void)hipGraphDestroy(p->graph);
+        p->exec = nullptr;
+        p->graph = nullptr;
+    }
     return TTM_OK;
 }
 

@@ -218,6 +218,11 @@ class BatchedPlan:
         check(self._lib.ttm_batched_plan_config(self._h, out), "ttm_batched_plan_config")
         return {"threads": out[0], "blocks_per_cu": out[1], "blocks": out[2], "variant": out[3]}
 
+    def set_config(self, threads: int, blocks_per_cu: int, variant: int) -> None:
+        """Pin the launch shape (ttm_batched_plan_set_config)."""
+        check(self._lib.ttm_batched_plan_set_config(self._h, int(threads), int(blocks_per_cu), int(variant),
+                                                    _stream(self.device)), "ttm_batched_plan_set_config")
+
 
 COMPACT6 = (1.0 / 3.0, 14.0 / 9.0, 1.0 / 9.0)   # alpha, a, b of Sec. 4.2 Eq. (cfds)
 

@@ -129,3 +129,31 @@ def test_c4_full_workload():
     Yg = plan.run(*bufs, mode="graph")
     torch.cuda.synchronize()
     assert np.array_equal(Yg.double().cpu().numpy(), Y)
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2], ids=["occ2-prefetch", "occ3", "occ4"])
+@pytest.mark.parametrize("threads", [64, 256])
+def test_every_launch_variant(variant, threads):
+    """Every kernel variant and block size gives the default shape's result
+    bit for bit (and the oracle's to 1e-5), on ragged sizes up to 16 (four
+    passes of 64 fibers)."""
+    rng = np.random.default_rng(30)
+    dims = ragged_dims(rng, 700, 1, 16)
+    p = workloads.random_batched(dims, seed=31, dtype=np.float32)
+    tdt = torch.float32
+    plan = BatchedPlan(p["dims"], dtype=tdt)
+    bufs = [dev(p[k], tdt) for k in "XABC"]
+    Y0 = plan.run(*bufs).cpu().numpy()
+    plan.set_config(threads, 1, variant)
+    cfg = plan.config()
+    assert cfg["threads"] == threads and cfg["blocks_per_cu"] == 1 and cfg["variant"] == variant
+    Y = plan.run(*bufs).cpu().numpy()
+    assert np.array_equal(Y, Y0)
+    Yg = plan.run(*bufs, mode="graph").cpu().numpy()
+    assert np.array_equal(Yg, Y0)
+    ref = oracle.batched(p["dims"], p["X"], p["A"], p["B"], p["C"])
+    assert pins.rel_fro(Y.astype(np.float64), ref) <= 1e-5
+    with pytest.raises(RuntimeError):
+        plan.set_config(96, 1, variant)
+    with pytest.raises(RuntimeError):
+        plan.set_config(threads, 1, 3)
