@@ -151,6 +151,7 @@ def test_batched_plan_validation_errors(lib):
     assert lib.ttm_batched_plan_destroy(None) == E.TTM_ERR_INVALID_ARG
     assert lib.ttm_batched_plan_totals(None, None) == E.TTM_ERR_INVALID_ARG
     assert lib.ttm_chain_batched(None, P(FAKE), P(FAKE), P(FAKE), P(FAKE), P(FAKE), P(0)) == E.TTM_ERR_INVALID_ARG
+    assert lib.ttm_batched_plan_set_config(None, 256, 1, 1, P(0)) == E.TTM_ERR_INVALID_ARG
 
 
 def test_timing_collect_empty(lib):
