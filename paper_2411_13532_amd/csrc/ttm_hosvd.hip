@@ -9,7 +9,11 @@
 // workgroup, G resident in LDS (I_n <= 128): each sweep visits every pair
 // (p, q) once, in rounds of I_n / 2 disjoint pairs (the round-robin
 // schedule), every round one set of plane rotations applied to the rows,
-// then the columns, of G and to the eigenvector matrix.
+// then the columns, of G.  The rotations are logged (c, s per pair and
+// round) instead of being applied to an eigenvector matrix: the product of
+// all of them, applied to the unit vectors of the J selected eigenvalues in
+// reverse order, gives those J eigenvectors alone, with no pass over an
+// n x n matrix in memory per round.
 // Sweeps repeat until the off-diagonal mass is below (I_n u)^2 of the
 // diagonal's, u = 2^-53 (at most 40): rounding alone keeps it near I_n u^2,
 // so a fixed tighter bound would run every sweep.  The eigenvalues sorted in
@@ -29,23 +33,33 @@ constexpr int EIG_NMAX = 128;
 constexpr int EIG_THREADS = 1024;
 constexpr int EIG_MAX_SWEEPS = 40;
 
-// Vt (n x n in global memory, row k = eigenvector k: the rotations then
-// touch two rows, contiguous in memory) and sorted outputs: rows r < J of U
+// The rotation log (per mode: EIG_MAX_SWEEPS * (m - 1) rounds of m / 2
+// (c, s) pairs, m = n rounded up to even) and sorted outputs: rows r < J of U
 // (J x n) and the n eigenvalues in decreasing order (nullable).  A sits in
 // LDS with rows padded to EIG_LDA doubles, so that the column updates of a
 // round (32 consecutive rows of one column per half-wave) hit distinct banks.
 // Thread t of a rotation phase takes pair t / 16 and elements (t % 16) + 16 m.
 constexpr int EIG_LDA = EIG_NMAX + 1;
+constexpr int EIG_RB = 8;    // rounds of rotations per prefetched block when rebuilding the eigenvectors
 // One workgroup per mode (the three solves are independent).
 struct JacobiArgs {
     const double *G[3];
-    double *Vt[3], *U[3], *evals[3];
+    double2 *log[3];
+    double *U[3], *evals[3];
     int n[3], J[3];
 };
+
+// Players p, q of pair k in round r of the round-robin schedule over m
+// players (m even): player m - 1 stays, the others rotate.
+__device__ __forceinline__ void rr_pair(int r, int k, int m, int &p, int &q) {
+    if (k == 0) { p = r; q = m - 1; }
+    else { p = (r + k) % (m - 1); q = (r - k + (m - 1)) % (m - 1); }
+}
 __global__ void __launch_bounds__(EIG_THREADS) k_sym_jacobi(const JacobiArgs ja) {
     const int mode = blockIdx.x;
     const double *G = ja.G[mode];
-    double *Vt = ja.Vt[mode], *U = ja.U[mode], *evals = ja.evals[mode];
+    double2 *rlog = ja.log[mode];
+    double *U = ja.U[mode], *evals = ja.evals[mode];
     const int n = ja.n[mode], J = ja.J[mode];
     __shared__ double A[EIG_NMAX * EIG_LDA];
     __shared__ double rc[EIG_NMAX / 2 + 1], rs[EIG_NMAX / 2 + 1];
@@ -57,19 +71,18 @@ __global__ void __launch_bounds__(EIG_THREADS) k_sym_jacobi(const JacobiArgs ja)
     for (int e = tid; e < n * n; e += EIG_THREADS) {
         const int i = e / n, j = e - i * n;
         A[i * EIG_LDA + j] = G[e];
-        Vt[e] = i == j ? 1.0 : 0.0;
     }
     const int m = n + (n & 1);          // players of the round-robin (one idle slot when n is odd)
     const int np = m / 2;
     const int pk = tid >> 4, e0 = tid & 15;   // pair and first element of this thread
+    int rounds = 0;                     // rounds logged
     __syncthreads();
     for (int sweep = 0; sweep < EIG_MAX_SWEEPS; ++sweep) {
-        for (int r = 0; r < m - 1; ++r) {
+        for (int r = 0; r < m - 1; ++r, ++rounds) {
             // rotation of every pair of this round
             if (tid < np) {
                 int p, q;
-                if (tid == 0) { p = r; q = m - 1; }
-                else { p = (r + tid) % (m - 1); q = (r - tid + (m - 1)) % (m - 1); }
+                rr_pair(r, tid, m, p, q);
                 double c = 1.0, s = 0.0;
                 if (p < n && q < n) {
                     const double apq = A[p * EIG_LDA + q];
@@ -86,22 +99,13 @@ __global__ void __launch_bounds__(EIG_THREADS) k_sym_jacobi(const JacobiArgs ja)
                 rq[tid] = q;
                 rc[tid] = c;
                 rs[tid] = s;
+                rlog[int64_t(rounds) * np + tid] = double2{c, s};
             }
             __syncthreads();
             const int p = pk < np ? rp[pk] : n, q = pk < np ? rq[pk] : n;
             const bool live = p < n && q < n;
             const double c = live ? rc[pk] : 1.0, s = live ? rs[pk] : 0.0;
-            // rows p and q of Vt: every load issued before the updates (one
-            // memory latency per round), stored after the barrier below
             constexpr int EPT = EIG_NMAX / 16;   // elements per thread
-            double vp[EPT], vq[EPT];
-            if (live)
-#pragma unroll
-                for (int u = 0; u < EPT; ++u) {
-                    const int i = e0 + 16 * u;
-                    vp[u] = i < n ? Vt[p * n + i] : 0.0;
-                    vq[u] = i < n ? Vt[q * n + i] : 0.0;
-                }
             // rows p and q of A
             if (live)
 #pragma unroll
@@ -123,8 +127,6 @@ __global__ void __launch_bounds__(EIG_THREADS) k_sym_jacobi(const JacobiArgs ja)
                         const double ap = A[i * EIG_LDA + p], aq = A[i * EIG_LDA + q];
                         A[i * EIG_LDA + p] = c * ap - s * aq;
                         A[i * EIG_LDA + q] = s * ap + c * aq;
-                        Vt[p * n + i] = c * vp[u] - s * vq[u];
-                        Vt[q * n + i] = s * vp[u] + c * vq[u];
                     }
                 }
             __syncthreads();
@@ -166,13 +168,62 @@ __global__ void __launch_bounds__(EIG_THREADS) k_sym_jacobi(const JacobiArgs ja)
     }
     __syncthreads();
     if (evals && tid < n) evals[tid] = A[order[tid] * EIG_LDA + order[tid]];
-// factor rows: one wave per row, sign fixed by the entry of largest magnitude
+    // Eigenvector of eigenvalue order[j], j < J: the rounds' rotations Q_k
+    // (rows p, q of a vector: x_p <- c x_p - s x_q, x_q <- s x_p + c x_q)
+    // turned the identity into the matrix whose rows are the eigenvectors,
+    // Q_K ... Q_1, so row order[j] is e^T Q_K ... Q_1 with e = e_order[j]:
+    // Q_K^T first, down to Q_1^T, on a vector started at e.  The vectors
+    // take A's place (its diagonal is read above); thread t owns pair t % 64
+    // of every round for the vectors t / 64, t / 64 + 16, ...  Each thread
+    // holds the (c, s) of its pair for a block of EIG_RB rounds and loads the
+    // next block while it applies the current one.
+    __syncthreads();
+    double *x = A;                      // J vectors of n, stride EIG_LDA
+    for (int e = tid; e < J * n; e += EIG_THREADS) {
+        const int j = e / n, i = e - j * n;
+        x[j * EIG_LDA + i] = i == order[j] ? 1.0 : 0.0;
+    }
+    const int k = tid & 63, j0 = tid >> 6;
+    const bool kin = k < np;
+    double2 cur[EIG_RB], nxt[EIG_RB];
+    auto load_block = [&](int top, double2 (&dst)[EIG_RB]) {   // rounds top, top - 1, ..., top - EIG_RB + 1
+#pragma unroll
+        for (int b = 0; b < EIG_RB; ++b) {
+            const int rd = top - b;
+            dst[b] = (kin && rd >= 0) ? rlog[int64_t(rd) * np + k] : double2{1.0, 0.0};
+        }
+    };
+    load_block(rounds - 1, cur);
+    __syncthreads();
+    for (int top = rounds - 1; top >= 0; top -= EIG_RB) {
+        if (top - EIG_RB >= 0) load_block(top - EIG_RB, nxt);
+#pragma unroll
+        for (int b = 0; b < EIG_RB; ++b) {
+            const int rd = top - b;
+            if (rd >= 0) {
+                int p, q;
+                rr_pair(rd % (m - 1), k, m, p, q);
+                if (kin && p < n && q < n) {
+                    const double c = cur[b].x, s = cur[b].y;
+                    for (int j = j0; j < J; j += EIG_THREADS / 64) {
+                        const double xp = x[j * EIG_LDA + p], xq = x[j * EIG_LDA + q];
+                        x[j * EIG_LDA + p] = c * xp + s * xq;
+                        x[j * EIG_LDA + q] = c * xq - s * xp;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < EIG_RB; ++b) cur[b] = nxt[b];
+    }
+    // factor rows: one wave per row, sign fixed by the entry of largest magnitude
     for (int row = wave; row < J; row += EIG_THREADS / 64) {
-        const int col = order[row];
+        const double *v = x + row * EIG_LDA;
         double best = -1.0;
         int bi = n;
         for (int i = lane; i < n; i += 64) {
-            const double a = fabs(Vt[col * n + i]);
+            const double a = fabs(v[i]);
             if (a > best || (a == best && i < bi)) { best = a; bi = i; }
         }
         for (int o = 32; o > 0; o >>= 1) {
@@ -180,15 +231,15 @@ __global__ void __launch_bounds__(EIG_THREADS) k_sym_jacobi(const JacobiArgs ja)
             const int oi = __shfl_xor(bi, o);
             if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
         }
-        const double sgn = Vt[col * n + bi] < 0.0 ? -1.0 : 1.0;
-        for (int i = lane; i < n; i += 64) U[int64_t(row) * n + i] = sgn * Vt[col * n + i];
+        const double sgn = v[bi] < 0.0 ? -1.0 : 1.0;
+        for (int i = lane; i < n; i += 64) U[int64_t(row) * n + i] = sgn * v[i];
     }
 }
 
 struct HosvdPlan {
     int64_t nmax;
     int ks[3];
-    size_t off_G[3], off_V[3], off_P, total;
+    size_t off_G[3], off_L[3], off_P, total;
 };
 
 static void hosvd_plan(const ttm_shape &s, HosvdPlan &p) {
@@ -205,11 +256,15 @@ static void hosvd_plan(const ttm_shape &s, HosvdPlan &p) {
         kmax = std::max(kmax, p.ks[n]);
     }
     const size_t nn = size_t(p.nmax * p.nmax) * 8, nn_al = (nn + 255) & ~size_t(255);
+    // rotation log: every round of the largest mode, (c, s) per pair
+    const int64_t mmax = p.nmax + (p.nmax & 1);
+    const size_t lg = size_t(EIG_MAX_SWEEPS) * size_t(std::max<int64_t>(mmax - 1, 1)) * size_t(mmax / 2) * 16;
+    const size_t lg_al = (lg + 255) & ~size_t(255);
     for (int n = 0; n < 3; ++n) {
         p.off_G[n] = size_t(n) * nn_al;
-        p.off_V[n] = size_t(3 + n) * nn_al;
+        p.off_L[n] = 3 * nn_al + size_t(n) * lg_al;
     }
-    p.off_P = 6 * nn_al;
+    p.off_P = 3 * nn_al + 3 * lg_al;
     p.total = p.off_P + (kmax > 1 ? size_t(kmax) * nn : 0);
 }
 
@@ -304,7 +359,7 @@ int ttm_hosvd(const ttm_shape *shape, const void *X, void *A, void *B, void *C, 
         double *G = reinterpret_cast<double *>(w + p.off_G[n]);
         if ((rc = gram_f64(s, static_cast<const double *>(X), n + 1, G, part, p.ks[n], st))) return rc;
         ja.G[n] = G;
-        ja.Vt[n] = reinterpret_cast<double *>(w + p.off_V[n]);
+        ja.log[n] = reinterpret_cast<double2 *>(w + p.off_L[n]);
         ja.U[n] = static_cast<double *>(outs[n]);
         ja.evals[n] = evals ? static_cast<double *>(evals) + eoff : nullptr;
         ja.n[n] = int(s.I[n]);
