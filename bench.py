@@ -326,11 +326,34 @@ def bench_c5(args, torch, ttm):
     ms_b = timed(bwd, args.steps, args.warmup, torch)["median"]
     kt_b = {k: n * v for k, (n, v) in kernel_times(bwd, args.steps, torch, ttm).items()}
     fl_f = chain_flops(I, J)
+    # dominant kernel of the step: the adjoint's X pass, which does the whole
+    # backward but the fixed-order sums of the dB and dC shares.  Algorithmic
+    # work of the backward: dX = G x1 A^T x2 B^T x3 C^T (the chain with J and
+    # I swapped), Z = X x2 B x3 C for dA, the dB path, and the three small
+    # GEMMs of dA, dB, dC; bytes: X read, dX written, G and the factors read,
+    # dA, dB, dC written
+    bwd_flops = chain_flops(I, J) + 2.0 * (J * I ** 3 + J * J * I * I) + 2.0 * J * J * I * I + 3 * 2.0 * J ** 3 * I
+    bwd_bytes = 2 * I ** 3 * 4 + J ** 3 * 4 + 2 * 3 * J * I * 4
+    roof = None
+    if "ttm_bwd_xpass" in kt_b:
+        xms = kt_b["ttm_bwd_xpass"]
+        gbs = bwd_bytes / (xms * 1e-3) / 1e9
+        tf = bwd_flops / (xms * 1e-3) / 1e12
+        if bwd_bytes / (HBM_PEAK_GBS * 1e9) >= bwd_flops / (F32_TFLOPS * 1e12):
+            roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(gbs / HBM_PEAK_GBS, 4)}
+        else:
+            roof = {"bound": "mfma", "achieved": round(tf, 2), "peak": F32_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(tf / F32_TFLOPS, 4)}
+        roof.update({"traffic": None, "kernel": "ttm_bwd_xpass (k_bwd_xpass_f32)", "kernel_ms": round(xms, 4),
+                     "algorithmic_bytes": bwd_bytes, "flops": bwd_flops,
+                     "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "mfma_frac": round(tf / F32_TFLOPS, 4)})
     return {"metric": "TTM-chain forward+adjoint GFLOP/s", "value": round(fl_f / ((ms_f) * 1e-3) / 1e9, 1),
             "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": round(ms_f + ms_b, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "f32", "data": "synthetic",
             "config": {"workload": "X 256^3 float32, factors 32x256 N(0,1/256), L = 1/2||Y - T||^2", "I": I, "J": J},
+            "roofline": roof,
             "forward_ms": round(ms_f, 4), "backward_ms": round(ms_b, 4),
             "backward_kernels_ms": {k: round(v, 4) for k, v in kt_b.items()}}
 
