@@ -138,8 +138,8 @@ def test_oracle_under_address_and_undefined_behavior_sanitizers(tmp_path):
     cmd = ["gcc", "-std=c11", "-O1", "-g", "-fno-omit-frame-pointer", "-ffp-contract=off", "-Wno-unknown-pragmas",
            "-fsanitize=address,undefined", "-fno-sanitize-recover=all", SRC, str(drv), "-lm", "-o", str(exe)]
     subprocess.run(cmd, check=True, capture_output=True)
-    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1")
-    env.pop("LD_PRELOAD", None)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0:verify_asan_link_order=0",
+               UBSAN_OPTIONS="print_stacktrace=1")
     r = subprocess.run([str(exe)], capture_output=True, text=True, env=env, timeout=120)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "oracle under sanitizers: ok" in r.stdout
