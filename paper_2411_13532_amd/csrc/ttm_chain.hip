@@ -643,7 +643,10 @@ __device__ __forceinline__ void slab_mode2_pipe(typename MathTraits<MATH>::accv_
 // therefore never adds a wait of its own for the copies in flight, which it
 // cannot tell apart by stage.  The 16-byte words of a 128-byte row are XOR-
 // swizzled by (row >> 1) & 7: the 16 rows of a fragment read cover all 64
-// banks.  The two row halves' V partials are added through LDS at the end.
+// banks.  At the end of a tile the mode-2 step copies B once per workgroup
+// into the tile's consumed X and C stages (mode2_lds below) for all eight
+// waves to read.  The two row halves' V partials are added through LDS at
+// the end.
 // ---------------------------------------------------------------------------
 constexpr int LC_THREADS = 512;
 constexpr int LC_TM = 256;
