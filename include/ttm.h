@@ -252,18 +252,22 @@ int ttm_batched_autotune(ttm_batched_plan *plan, const void *X, const void *A,
 
 /* The plan's current launch shape (out holds 4 ints): out[0] = threads per
  * block, out[1] = resident blocks per compute unit, out[2] = total blocks,
- * out[3] = kernel variant (float: 0 keeps the next cuboid's inputs in
- * registers at two waves per SIMD, 1 and 2 run three and four waves per
- * SIMD without; double: every variant runs the same kernel). */
+ * out[3] = kernel variant (float, mode products on the vector units: 0
+ * keeps the next cuboid's inputs in registers at two waves per SIMD, 1 and 2
+ * run three and four waves per SIMD without; on the matrix cores: 3 at three
+ * waves per SIMD with a shorter prefetch, 4 at four without; double: every
+ * variant runs the same kernel). */
 int ttm_batched_plan_config(const ttm_batched_plan *plan, int *out);
 
 /* Pins the plan's launch shape, as the autotuner does with its choice:
  * threads per block (64, 128 or 256), resident blocks per compute unit (at
  * least 1 and at most what LDS and the variant's registers allow) and the
- * variant (0, 1 or 2, as in ttm_batched_plan_config).  Rebuilds the
- * assignment of cuboids to waves (synchronising `stream`); the results of
- * every shape are identical.  TTM_ERR_INVALID_ARG for a shape outside these
- * ranges, TTM_ERR_HIP. */
+ * variant (0 to 4, as in ttm_batched_plan_config).  Rebuilds the
+ * assignment of cuboids to waves (synchronising `stream`).  The results of
+ * every shape are identical among the vector-unit variants (0-2) and among
+ * the matrix-core variants (3, 4); the two families sum the terms of each
+ * output in different orders (both to float rounding of the exact result).
+ * TTM_ERR_INVALID_ARG for a shape outside these ranges, TTM_ERR_HIP. */
 int ttm_batched_plan_set_config(ttm_batched_plan *plan, int threads, int blocks_per_cu, int variant,
                                 void *stream);
 

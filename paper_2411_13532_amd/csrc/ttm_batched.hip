@@ -21,6 +21,13 @@
 // The next cuboid's X and factors are loaded into registers while the wave
 // works on the current one.
 //
+// The matrix-core variants (MX) form each mode product as 16 x 16 x 4 float
+// products instead (mode_mfma): the factor is the A operand, held in
+// registers, and 16 fibers form the B operand of each tile, read from the
+// same LDS region.  The wave's time per cuboid is mostly the latency of its
+// dependent steps (load X, three products, store Y), so the gain over the
+// vector units is small; the kernel runs as fast as resident waves allow.
+//
 // Work assignment: the plan sorts the cuboids longest first and deals them
 // to the waves of the launch by LPT (each to the wave with the least work so
 // far, by a cost model of the passes and dot products above); wave w runs
@@ -172,17 +179,96 @@ __device__ __forceinline__ void mode_any(const T *buf, int NF, int L, const T *U
 #undef TTM_MODE_CASE
 }
 
+// One mode product on the matrix cores (float): D[j][f] = sum_{k < L}
+// U[j][k] x_f[k] for j < M (<= 16) and fibers f < NF (<= 16 * NTM) of length
+// L (<= 4 * KS), as 16 x 16 x 4 products, one 16-fiber tile per accumulator.
+// The factor is the A operand: lane l holds row l % 16 and the k slots
+// (l / 16) * KS + s in ua[s] (zero past M and L).  The fibers are the B
+// operand: column l % 16 of tile t is fiber 16 t + l % 16, its k slots read
+// from buf[rbase(f) + k * rstride], the fiber and k clamped to valid elements
+// where the factor slot is zero (the value only has to be finite).  Lane l's
+// accumulator element r is D[4 (l / 16) + r][16 t + l % 16], written to
+// out[obase(f) + j * ostride].  Every tile is formed before any output is
+// written, so the outputs may overwrite the fibers (the caller syncs the wave
+// before and after).  Fixed order of the terms.
+template <int KS, int NTM, typename RB, typename OB>
+__device__ __forceinline__ void mode_mfma_body(const float *buf, int NF, int L, const float (&ua)[4], int M, RB rbase,
+                                               int rstride, float *lout, float *gout, OB obase, int ostride,
+                                               int lane) {
+    const int c = lane & 15, g = lane >> 4;
+    const int NT = (NF + 15) >> 4;
+    int kofs[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+        const int k = g * KS + s;
+        kofs[s] = (k < L ? k : L - 1) * rstride;
+    }
+    f32x4 acc[NTM];
+#pragma unroll
+    for (int t = 0; t < NTM; ++t) {
+        if (t < NT) {   // uniform
+            const int f = t * 16 + c;
+            const int b = rbase(f < NF ? f : NF - 1);
+            float x[KS];
+#pragma unroll
+            for (int s = 0; s < KS; ++s) x[s] = buf[b + kofs[s]];
+            acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < KS; ++s) acc[t] = mfma_f32(ua[s], x[s], acc[t]);
+        }
+    }
+    wave_sync();   // every tile is formed: the outputs may overwrite the fibers
+#pragma unroll
+    for (int t = 0; t < NTM; ++t) {
+        const int f = t * 16 + c;
+        if (t < NT && f < NF) {
+            const int64_t o = obase(f);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = 4 * g + r;
+                if (j < M) {
+                    if (gout) gout[o + int64_t(j) * ostride] = acc[t][r];
+                    else lout[o + j * ostride] = acc[t][r];
+                }
+            }
+        }
+    }
+}
+
+// mode_mfma_body for runtime L (1..16) and NF (1..256)
+template <typename RB, typename OB>
+__device__ __forceinline__ void mode_mfma(const float *buf, int NF, int L, const float (&ua)[4], int M, RB rbase,
+                                          int rstride, float *lout, float *gout, OB obase, int ostride, int lane) {
+    const int KS = (L + 3) >> 2, NTQ = (NF + 63) >> 6;
+#define TTM_MX_CASE(ks, ntq)                                                                              \
+    case (ks - 1) * 4 + (ntq - 1):                                                                        \
+        mode_mfma_body<ks, 4 * ntq>(buf, NF, L, ua, M, rbase, rstride, lout, gout, obase, ostride, lane); \
+        break;
+    switch ((KS - 1) * 4 + (NTQ - 1)) {
+        TTM_MX_CASE(1, 1) TTM_MX_CASE(1, 2) TTM_MX_CASE(1, 3) TTM_MX_CASE(1, 4)
+        TTM_MX_CASE(2, 1) TTM_MX_CASE(2, 2) TTM_MX_CASE(2, 3) TTM_MX_CASE(2, 4)
+        TTM_MX_CASE(3, 1) TTM_MX_CASE(3, 2) TTM_MX_CASE(3, 3) TTM_MX_CASE(3, 4)
+        TTM_MX_CASE(4, 1) TTM_MX_CASE(4, 2) TTM_MX_CASE(4, 3) TTM_MX_CASE(4, 4)
+        default: break;
+    }
+#undef TTM_MX_CASE
+}
+
 // OCC: resident waves per SIMD the register budget is cut for (a launch
 // variant the autotuner chooses).  At two, the next cuboid's first
 // BATCH_PF * 64 elements of X and its factors are loaded into registers while
-// the wave works on the current one; at three or more there is no room for
-// that, and the other resident waves cover the load latency instead.
-template <typename T, int OCC>
+// the wave works on the current one (with MX at three, half as many rows of
+// X); otherwise there is no room for that, and the other resident waves
+// cover the load latency instead.
+// MX: the mode products on the matrix cores (mode_mfma, float only); the
+// factors then stay in registers in the A-operand layout and the LDS factor
+// region is unused.
+template <typename T, int OCC, bool MX = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
 k_batched(const BatchArgs a, const T *__restrict__ X, const T *__restrict__ Ag, const T *__restrict__ Bg,
           const T *__restrict__ Cg, T *__restrict__ Y) {
-    constexpr int PF = OCC <= 2 ? BATCH_PF : 0;
-    constexpr int PFF = OCC <= 2 ? 4 : 1;
+    constexpr int PF = OCC <= 2 ? BATCH_PF : MX && OCC == 3 ? BATCH_PF / 2 : 0;
+    constexpr int PFF = PF > 0 ? 4 : 1;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
@@ -204,7 +290,28 @@ k_batched(const BatchArgs a, const T *__restrict__ X, const T *__restrict__ Ag, 
     // the first PF rows of 64 elements of a cuboid's X and its three factors
     // (at most 256 elements each, 4 per lane); fr: the current cuboid's
     // factors until their modes
-    T pre[PF > 0 ? PF : 1], pf[3][PFF], fr[3][4];
+    static_assert(!MX || std::is_same<T, float>::value, "matrix-core variant is float only");
+    T pre[PF > 0 ? PF : 1], pf[3][4], fr[3][4];
+    // a factor U (J x I) into four registers per lane: elements u * 64 + lane
+    // (rows of 64 the factor fills), or with MX the A-operand slots of
+    // mode_mfma (row lane % 16, k = (lane / 16) * KS + s, zero elsewhere)
+    auto load_factor = [&](const T *U, int J, int I, T (&dst)[4]) __attribute__((always_inline)) {
+        if constexpr (MX) {
+            const int c = lane & 15, g = lane >> 4, KS = (I + 3) >> 2;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int k = g * KS + s;
+                dst[s] = (c < J && s < KS && k < I) ? U[c * I + k] : T(0);
+            }
+        } else {
+            const int n = J * I;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = u * 64 + lane;
+                if (u * 64 < n) dst[u] = U[e < n ? e : n - 1];   // uniform: rows of 64 the factor fills
+            }
+        }
+    };
     auto load_inputs = [&](const CuboidDesc &d) __attribute__((always_inline)) {
         const int nx = d.d[0] * d.d[1] * d.d[2];
         const T *xs = X + d.ox;
@@ -218,14 +325,7 @@ k_batched(const BatchArgs a, const T *__restrict__ X, const T *__restrict__ Ag, 
         if constexpr (PF > 0) {
             const T *fs[3] = {Ag + d.oa, Bg + d.ob, Cg + d.oc};
 #pragma unroll
-            for (int f = 0; f < 3; ++f) {
-                const int n = d.d[3 + f] * d.d[f];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int e = u * 64 + lane;
-                    if (u * 64 < n) pf[f][u] = fs[f][e < n ? e : n - 1];
-                }
-            }
+            for (int f = 0; f < 3; ++f) load_factor(fs[f], d.d[3 + f], d.d[f], pf[f]);
         }
     };
     auto prefetch = [&](const CuboidDesc &d) __attribute__((always_inline)) {
@@ -250,17 +350,22 @@ k_batched(const BatchArgs a, const T *__restrict__ X, const T *__restrict__ Ag, 
                 for (int u = 0; u < 4; ++u) fr[f][u] = pf[f][u];
         } else {
             const T *fs[3] = {Ag + d.oa, Bg + d.ob, Cg + d.oc};
+            if constexpr (MX) {
 #pragma unroll
-            for (int f = 0; f < 3; ++f) {
-                const int n = d.d[3 + f] * d.d[f];
+                for (int f = 0; f < 3; ++f) load_factor(fs[f], d.d[3 + f], d.d[f], fr[f]);
+            } else {
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int e = u * 64 + lane;
-                    if (u * 64 < n) fr[f][u] = fs[f][e < n ? e : n - 1];   // uniform: rows of 64 the factor fills
+                for (int f = 0; f < 3; ++f) {
+                    const int n = d.d[3 + f] * d.d[f];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int e = u * 64 + lane;
+                        if (u * 64 < n) fr[f][u] = fs[f][e < n ? e : n - 1];   // uniform: rows of 64 the factor fills
+                    }
                 }
             }
         }
-        factor_regs_to_lds(fr[2], J3 * I3, I3, P3, fac, lane);
+        if constexpr (!MX) factor_regs_to_lds(fr[2], J3 * I3, I3, P3, fac, lane);
         const int SX = I3 | 1;
         const float inv3 = __builtin_amdgcn_rcpf(float(I3));
 #pragma unroll
@@ -290,25 +395,32 @@ k_batched(const BatchArgs a, const T *__restrict__ X, const T *__restrict__ Ag, 
 
         // mode 3: fiber f = (i1, i2) along i3 -> W[f][j3] at row stride SW
         const int SW = J3 | 1;
-        mode_any(buf, I1 * I2, I3, fac, P3, J3, [&](int f) { return f * SX; }, 1, buf, static_cast<T *>(nullptr),
-                 [&](int f) { return f * SW; }, 1, lane);
+        auto rb3 = [&](int f) { return f * SX; };
+        auto ob3 = [&](int f) { return f * SW; };
+        if constexpr (MX) mode_mfma(buf, I1 * I2, I3, fr[2], J3, rb3, 1, buf, static_cast<T *>(nullptr), ob3, 1, lane);
+        else mode_any(buf, I1 * I2, I3, fac, P3, J3, rb3, 1, buf, static_cast<T *>(nullptr), ob3, 1, lane);
         wave_sync();
-        factor_regs_to_lds(fr[1], J2 * I2, I2, P2, fac, lane);
-        wave_sync();
+        if constexpr (!MX) {
+            factor_regs_to_lds(fr[1], J2 * I2, I2, P2, fac, lane);
+            wave_sync();
+        }
         // mode 2: fiber g = (i1, j3) along i2 -> V[i1][j2][j3] at i1 stride SV
         const int SV = (J2 * J3) | 1;
         const float invJ3 = __builtin_amdgcn_rcpf(float(J3));
-        mode_any(buf, I1 * J3, I2, fac, P2, J2,
-                 [&](int g) { const int i1 = row_of(g, invJ3); return i1 * I2 * SW + (g - i1 * J3); }, SW, buf,
-                 static_cast<T *>(nullptr), [&](int g) { const int i1 = row_of(g, invJ3); return i1 * SV + (g - i1 * J3); },
-                 J3, lane);
+        auto rb2 = [&](int g) { const int i1 = row_of(g, invJ3); return i1 * I2 * SW + (g - i1 * J3); };
+        auto ob2 = [&](int g) { const int i1 = row_of(g, invJ3); return i1 * SV + (g - i1 * J3); };
+        if constexpr (MX) mode_mfma(buf, I1 * J3, I2, fr[1], J2, rb2, SW, buf, static_cast<T *>(nullptr), ob2, J3, lane);
+        else mode_any(buf, I1 * J3, I2, fac, P2, J2, rb2, SW, buf, static_cast<T *>(nullptr), ob2, J3, lane);
         wave_sync();
-        factor_regs_to_lds(fr[0], J1 * I1, I1, P1, fac, lane);
-        wave_sync();
+        if constexpr (!MX) {
+            factor_regs_to_lds(fr[0], J1 * I1, I1, P1, fac, lane);
+            wave_sync();
+        }
         // mode 1: fiber h = (j2, j3) along i1 -> Y[j1][h]
         const int H = J2 * J3;
-        mode_any(buf, H, I1, fac, P1, J1, [&](int h) { return h; }, SV, buf, Y + d.oy, [&](int h) { return h; }, H,
-                 lane);
+        auto rb1 = [&](int h) { return h; };
+        if constexpr (MX) mode_mfma(buf, H, I1, fr[0], J1, rb1, SV, buf, Y + d.oy, rb1, H, lane);
+        else mode_any(buf, H, I1, fac, P1, J1, rb1, SV, buf, Y + d.oy, rb1, H, lane);
         wave_sync();
     }
 }
@@ -349,7 +461,8 @@ size_t lds_per_wave(const ttm_batched_plan *p) { return size_t(p->fac_elems + p-
 
 // resident waves per SIMD the register budget of a launch variant allows
 int variant_occupancy(int dtype, int variant) {
-    return dtype == TTM_F64 ? 1 : variant + 2;
+    if (dtype == TTM_F64) return 1;
+    return variant < 3 ? variant + 2 : variant == 3 ? 3 : 4;
 }
 
 int max_blocks_per_cu(const ttm_batched_plan *p, int threads, int variant) {
@@ -415,15 +528,22 @@ BatchArgs make_args(const ttm_batched_plan *p) {
 }
 
 // Launch variants: the register budget of k_batched (resident waves per
-// SIMD).  float: 2 (with register prefetch of the next cuboid), 3 or 4;
-// double: 1 for all.
-constexpr int BATCH_VARIANTS = 3;
+// SIMD) and where the mode products run.  float: 0, 1, 2 on the vector units
+// at 2 (with register prefetch of the next cuboid), 3 or 4 waves per SIMD;
+// 3 and 4 on the matrix cores at 3 (prefetching the next cuboid's factors and
+// first 512 elements of X) or 4.  double: one kernel (1 wave per SIMD, vector
+// units) for every variant.
+constexpr int BATCH_VARIANTS = 5;
 const void *kernel_ptr(int dtype, int variant) {
     if (dtype == TTM_F64)
         return reinterpret_cast<const void *>(&k_batched<double, 1>);
-    return variant == 0 ? reinterpret_cast<const void *>(&k_batched<float, 2>)
-         : variant == 1 ? reinterpret_cast<const void *>(&k_batched<float, 3>)
-                        : reinterpret_cast<const void *>(&k_batched<float, 4>);
+    switch (variant) {
+        case 0: return reinterpret_cast<const void *>(&k_batched<float, 2>);
+        case 1: return reinterpret_cast<const void *>(&k_batched<float, 3>);
+        case 2: return reinterpret_cast<const void *>(&k_batched<float, 4>);
+        case 3: return reinterpret_cast<const void *>(&k_batched<float, 3, true>);
+        default: return reinterpret_cast<const void *>(&k_batched<float, 4, true>);
+    }
 }
 template <typename T>
 void launch_variant(int variant, dim3 grid, dim3 block, size_t lds, hipStream_t st, const BatchArgs &a, const void *X,
@@ -434,7 +554,9 @@ void launch_variant(int variant, dim3 grid, dim3 block, size_t lds, hipStream_t 
     constexpr bool F = std::is_same<T, float>::value;
     if (variant == 0 || !F) hipLaunchKernelGGL((k_batched<T, F ? 2 : 1>), grid, block, lds, st, a, x, pa, pb, pc, y);
     else if (variant == 1) hipLaunchKernelGGL((k_batched<T, F ? 3 : 1>), grid, block, lds, st, a, x, pa, pb, pc, y);
-    else hipLaunchKernelGGL((k_batched<T, F ? 4 : 1>), grid, block, lds, st, a, x, pa, pb, pc, y);
+    else if (variant == 2) hipLaunchKernelGGL((k_batched<T, F ? 4 : 1>), grid, block, lds, st, a, x, pa, pb, pc, y);
+    else if (variant == 3) hipLaunchKernelGGL((k_batched<T, F ? 3 : 1, F>), grid, block, lds, st, a, x, pa, pb, pc, y);
+    else hipLaunchKernelGGL((k_batched<T, F ? 4 : 1, F>), grid, block, lds, st, a, x, pa, pb, pc, y);
 }
 
 // One launch of the persistent kernel with the plan's current assignment
@@ -616,7 +738,7 @@ int ttm_batched_plan_create(int64_t count, const int64_t *dims_host, int dtype, 
     for (int64_t k = 0; k < count * 6; ++k) maxd = std::max(maxd, dims_host[k]);
     for (int64_t k = 0; k < count; ++k) sumc += p->cost[size_t(k)];
     char key[256];
-    snprintf(key, sizeof key, "%s|%s|v3|maxn%lld|count%lld|cost%lld", arch_name().c_str(),
+    snprintf(key, sizeof key, "%s|%s|v4|maxn%lld|count%lld|cost%lld", arch_name().c_str(),
              dtype == TTM_F64 ? "f64" : "f32", (long long)maxd, (long long)count, (long long)(sumc / count * 100));
     p->tune_key = key;
     if (tune_cache) {

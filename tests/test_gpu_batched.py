@@ -104,7 +104,11 @@ def test_deterministic_and_autotune(tmp_path):
     cfg = plan.config()
     assert cfg["threads"] in (64, 128, 256) and cfg["blocks_per_cu"] >= 1
     Y2 = plan.run(*bufs).cpu().numpy()
-    assert np.array_equal(Y0, Y2)       # the launch shape does not change the arithmetic
+    if cfg["variant"] in (0, 1, 2):
+        assert np.array_equal(Y0, Y2)   # the launch shape does not change the arithmetic
+    else:                               # matrix cores: another order of the terms
+        ref = oracle.batched(p["dims"], p["X"], p["A"], p["B"], p["C"])
+        assert pins.rel_fro(Y2.astype(np.float64), ref) <= 1e-5
     assert os.path.exists(cache)
     plan2 = BatchedPlan(p["dims"], dtype=tdt, tune_cache=cache)
     assert plan2.config()["threads"] == cfg["threads"]
@@ -131,18 +135,26 @@ def test_c4_full_workload():
     assert np.array_equal(Yg.double().cpu().numpy(), Y)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2], ids=["occ2-prefetch", "occ3", "occ4"])
+VECTOR_VARIANTS = (0, 1, 2)     # mode products on the vector units
+MATRIX_VARIANTS = (3, 4)        # mode products on the matrix cores
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4],
+                         ids=["occ2-prefetch", "occ3", "occ4", "mfma-occ3-prefetch", "mfma-occ4"])
 @pytest.mark.parametrize("threads", [64, 256])
 def test_every_launch_variant(variant, threads):
-    """Every kernel variant and block size gives the default shape's result
-    bit for bit (and the oracle's to 1e-5), on ragged sizes up to 16 (four
-    passes of 64 fibers)."""
+    """Every kernel variant and block size gives the oracle's result to 1e-5
+    on ragged sizes up to 16 (four passes of 64 fibers, sixteen tiles of 16),
+    and the result of every other variant of its arithmetic (vector units:
+    the default shape; matrix cores: variant 3 at 256 threads) bit for bit."""
     rng = np.random.default_rng(30)
     dims = ragged_dims(rng, 700, 1, 16)
     p = workloads.random_batched(dims, seed=31, dtype=np.float32)
     tdt = torch.float32
     plan = BatchedPlan(p["dims"], dtype=tdt)
     bufs = [dev(p[k], tdt) for k in "XABC"]
+    if variant in MATRIX_VARIANTS:
+        plan.set_config(256, 1, 3)
     Y0 = plan.run(*bufs).cpu().numpy()
     plan.set_config(threads, 1, variant)
     cfg = plan.config()
@@ -156,4 +168,61 @@ def test_every_launch_variant(variant, threads):
     with pytest.raises(RuntimeError):
         plan.set_config(96, 1, variant)
     with pytest.raises(RuntimeError):
-        plan.set_config(threads, 1, 3)
+        plan.set_config(threads, 1, 5)
+
+
+@pytest.mark.parametrize("variant", MATRIX_VARIANTS, ids=["mfma-occ3-prefetch", "mfma-occ4"])
+@pytest.mark.parametrize("dims", [
+    [(1, 1, 1, 1, 1, 1)],
+    [(13, 13, 13, 13, 13, 13)],
+    [(16, 16, 16, 16, 16, 16)] * 3,
+    [(5, 5, 5, 5, 5, 5)] * 500,
+    [(16, 1, 16, 1, 16, 1), (1, 16, 1, 16, 1, 16)],
+    [(3, 16, 7, 16, 2, 9), (16, 2, 5, 1, 16, 16), (9, 9, 16, 4, 13, 1)],
+], ids=["single-1", "single-13", "max-16", "all-5", "skinny", "mixed-ragged"])
+def test_matrix_core_variant_edges(variant, dims):
+    """The matrix-core variants on single elements, the largest cuboids (16
+    tiles, four k steps), many equal small ones, skinny and mixed shapes
+    (fibers and outputs that end inside a tile, k slots past the fiber)."""
+    p = workloads.random_batched(dims, seed=33, dtype=np.float32)
+    tdt = torch.float32
+    plan = BatchedPlan(p["dims"], dtype=tdt)
+    plan.set_config(256 if len(dims) > 8 else 64, 1, variant)
+    bufs = [dev(p[k], tdt) for k in "XABC"]
+    Y = plan.run(*bufs).double().cpu().numpy()
+    ref = oracle.batched(p["dims"], p["X"], p["A"], p["B"], p["C"])
+    assert pins.rel_fro(Y, ref) <= 1e-5
+
+
+@pytest.mark.parametrize("variant", MATRIX_VARIANTS, ids=["mfma-occ3-prefetch", "mfma-occ4"])
+def test_matrix_core_exact_integers_bitwise(variant):
+    rng = np.random.default_rng(34)
+    dims = ragged_dims(rng, 200, 1, 16)
+    p = workloads.random_batched(dims, seed=35, dtype=np.float64)
+    for k in "XABC":
+        p[k] = np.round(p[k] * 2.0).clip(-3, 3)
+    tdt = torch.float32
+    plan = BatchedPlan(p["dims"], dtype=tdt)
+    plan.set_config(256, 1, variant)
+    bufs = [dev(p[k], tdt) for k in "XABC"]
+    Y = plan.run(*bufs).double().cpu().numpy()
+    ref = oracle.batched(p["dims"], p["X"], p["A"], p["B"], p["C"])
+    assert np.array_equal(Y, ref)
+
+
+def test_c4_full_workload_matrix_cores():
+    """The c4 batch through the matrix-core variant, every cuboid to 1e-5."""
+    p = workloads.batched()
+    tdt = torch.float32
+    plan = BatchedPlan(p["dims"], dtype=tdt)
+    plan.set_config(256, 1, 4)
+    Y, _, bufs = run_plan(p, np.float32, plan=plan)
+    ref = oracle.batched(p["dims"], p["X"], p["A"], p["B"], p["C"])
+    off = 0
+    worst = 0.0
+    for d in p["dims"]:
+        n = int(d[3] * d[4] * d[5])
+        worst = max(worst, pins.rel_fro(Y[off:off + n], ref[off:off + n]))
+        off += n
+    print(f"[c4 matrix cores] rel err {pins.rel_fro(Y, ref):.3e}, worst cuboid {worst:.3e}", flush=True)
+    assert pins.rel_fro(Y, ref) <= 1e-5 and worst <= 1e-5
