@@ -47,20 +47,22 @@ def chain_flops(I, J):
     return 2.0 * (J * I ** 3 + J * J * I * I + J ** 3 * I)
 
 
-# the sources the chain kernels (the slab kernel among them) are built from
+# the sources the chain kernels (the slab kernel among them) are built from,
+# and those of the batched kernel
 CHAIN_SOURCES = ("ttm_chain.hip", "ttm_device.hpp", "ttm_host.hpp")
+BATCHED_SOURCES = ("ttm_batched.hip", "ttm_device.hpp", "ttm_host.hpp")
 
 
-def kernel_src_sha():
+def kernel_src_sha(sources=CHAIN_SOURCES):
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2411_13532_amd", "csrc")
-    for name in CHAIN_SOURCES:
+    for name in sources:
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(tag, per_launch_units=1.0):
+def measured_traffic(tag, per_launch_units=1.0, sources=CHAIN_SOURCES):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when there is none or the kernels changed since it was taken."""
     path = os.path.join(PROFILES, f"{tag}_traffic.json")
@@ -68,7 +70,7 @@ def measured_traffic(tag, per_launch_units=1.0):
         return None
     with open(path) as f:
         t = json.load(f)
-    if t.get("kernel_src_sha") != kernel_src_sha():
+    if t.get("kernel_src_sha") != kernel_src_sha(sources):
         return None
     return float(t["bytes_per_launch"]) * per_launch_units
 
@@ -266,6 +268,18 @@ def bench_c2(args, torch, ttm):
             "forms": res}
 
 
+def c4_traffic(variant):
+    """The batched kernel's measured HBM bytes per launch, when the launch
+    runs the variant the counters were taken on."""
+    path = os.path.join(PROFILES, "ttm_batched_c4_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        if json.load(f).get("variant") != variant:
+            return None
+    return measured_traffic("ttm_batched_c4", sources=BATCHED_SOURCES)
+
+
 def bench_c4(args, torch, ttm):
     from paper_2411_13532_amd import BatchedPlan, workloads
     p = workloads.batched()
@@ -276,7 +290,13 @@ def bench_c4(args, torch, ttm):
     flops = float(np.sum(6.0 * p["dims"][:, 0].astype(np.float64) ** 4))
     nbytes = 4.0 * sum(b.numel() for b in bufs) + 4.0 * Y.numel()
     flush = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
-    best = plan.autotune(*bufs, Y=Y, reps=5)
+    if args.c4_config:
+        # a pinned launch shape (for counter runs of one kernel shape)
+        threads, bpc, variant = (int(v) for v in args.c4_config.split(","))
+        plan.set_config(threads, bpc, variant)
+        best = None
+    else:
+        best = plan.autotune(*bufs, Y=Y, reps=5)
 
     def cold(mode):
         flush.fill_(1)   # evict the 256 MB last-level cache between steps
@@ -305,7 +325,9 @@ def bench_c4(args, torch, ttm):
             "config": {"workload": "20000 cuboids n^3, n ~ U{5..13} seed 3, square factors N(0,1/n); float32",
                        "count": 20000, "config": plan.config(), "autotune_best_ms": best},
             "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "ttm_batched"},
+                         "frac": round(gbs / HBM_PEAK_GBS, 4),
+                         "traffic": c4_traffic(plan.config()["variant"]),
+                         "kernel": "ttm_batched"},
             "persistent_ms": round(res["persistent"], 5), "graph_ms": round(res["graph"], 5),
             "per_cuboid_loop_ms": round(ms_loop, 3), "loop_over_graph": round(ms_loop / ms, 1)}
 
@@ -472,6 +494,8 @@ def main():
     ap.add_argument("--forms", default="bf16x3,f32,bf16",
                     help="c3: arithmetic forms to run (bf16x3 is the headline and must be included)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--c4-config", default="",
+                    help="c4: threads,blocks_per_cu,variant of the batched launch instead of autotuning")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
