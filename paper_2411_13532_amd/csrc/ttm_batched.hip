@@ -880,7 +880,8 @@ int ttm_batched_autotune(ttm_batched_plan *p, const void *X, const void *A, cons
     const int bpc_c[9] = {1, 2, 3, 4, 6, 8, 12, 16, 24};
     const bool was_timing = timing_on();
     if (was_timing) ttm_timing_enable(0);
-    for (int v = 0; v < BATCH_VARIANTS && rc == TTM_OK; ++v) {
+    const int nvar = p->dtype == TTM_F64 ? 1 : BATCH_VARIANTS;   // double: one kernel for every variant
+    for (int v = 0; v < nvar && rc == TTM_OK; ++v) {
         for (int ti = 0; ti < 3 && rc == TTM_OK; ++ti) {
             const int t = threads_c[ti];
             const int maxb = max_blocks_per_cu(p, t, v);

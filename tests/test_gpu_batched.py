@@ -115,6 +115,21 @@ def test_deterministic_and_autotune(tmp_path):
     assert plan2.config()["blocks_per_cu"] == cfg["blocks_per_cu"]
 
 
+def test_autotune_double():
+    """float64 has one kernel: the autotuner only picks the launch shape, and
+    the result stays bit for bit."""
+    rng = np.random.default_rng(36)
+    dims = ragged_dims(rng, 400, 1, 16)
+    p = workloads.random_batched(dims, seed=37, dtype=np.float64)
+    Y0, plan, bufs = run_plan(p, np.float64)
+    best = plan.autotune(*bufs, reps=1)
+    assert best > 0 and plan.config()["variant"] == 0
+    Y1 = plan.run(*bufs).cpu().numpy()
+    assert np.array_equal(Y1, Y0)
+    ref = oracle.batched(p["dims"], p["X"], p["A"], p["B"], p["C"])
+    assert pins.rel_fro(Y1, ref) <= 1e-12
+
+
 def test_c4_full_workload():
     """20000 cuboids n ~ U{5..13}, square factors N(0, 1/n), float32."""
     p = workloads.batched()
