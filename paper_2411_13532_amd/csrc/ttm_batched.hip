@@ -30,7 +30,8 @@
 //
 // Work assignment: the plan sorts the cuboids longest first and deals them
 // to the waves of the launch by LPT (each to the wave with the least work so
-// far, by a cost model of the passes and dot products above); wave w runs
+// far, by a cost model of the passes and dot products above plus a fixed
+// term per cuboid for its chain of dependent steps); wave w runs
 // its list desc[start[w] .. start[w + 1]).  The launch shape (threads per
 // block, resident blocks per compute unit) is autotuned per workload on a
 // cold last-level cache and cached; the assignment follows the shape.
@@ -67,6 +68,10 @@ struct BatchArgs {
 // every load issued before any is used) while the wave works on the current
 // one; a larger X loads its rest at stage 0.
 constexpr int BATCH_PF = 16;
+
+// fixed part of a cuboid's cost in the work assignment (units of the
+// per-mode pass x group x group terms)
+constexpr double BATCH_CUBOID_COST = 100.0;
 
 // Row r = e / len for e < 4096, len <= 16: the float quotient is at least
 // 1/32 away from the next integer, far more than its rounding error (also
@@ -672,7 +677,11 @@ int ttm_batched_plan_create(int64_t count, const int64_t *dims_host, int dtype, 
 
     // offsets in input order; per-wave LDS for the largest cuboid; the cost
     // model: per mode, passes of 64 fibers x groups of 4 along the fiber x
-    // groups of 4 outputs, plus the load of X
+    // groups of 4 outputs, plus the load of X, plus a fixed term for the
+    // cuboid's chain of dependent steps (load, three products, store), whose
+    // latency a wave pays per cuboid whatever its size: without it, waves
+    // dealt many small cuboids finish last (measured: any fixed term from 80
+    // up balances the same, 4 % faster than none)
     p->desc.resize(size_t(count));
     p->cost.resize(size_t(count));
     int64_t o[5] = {0, 0, 0, 0, 0};
@@ -689,7 +698,8 @@ int ttm_batched_plan_create(int64_t count, const int64_t *dims_host, int dtype, 
         auto g4 = [](int64_t v) { return double(ceil_div(v, 4)); };
         auto ps = [](int64_t v) { return double(ceil_div(v, 64)); };
         p->cost[size_t(k)] = ps(d[0] * d[1]) * g4(d[2]) * g4(d[5]) + ps(d[0] * d[5]) * g4(d[1]) * g4(d[4]) +
-                             ps(d[4] * d[5]) * g4(d[0]) * g4(d[3]) + double(ceil_div(d[0] * d[1] * d[2], 64));
+                             ps(d[4] * d[5]) * g4(d[0]) * g4(d[3]) + double(ceil_div(d[0] * d[1] * d[2], 64)) +
+                             BATCH_CUBOID_COST;
         p->fac_elems = std::max<int>(p->fac_elems, int(std::max({d[3] * round_up(d[0], 4), d[4] * round_up(d[1], 4),
                                                                   d[5] * round_up(d[2], 4)})));
         p->buf_elems = std::max<int>(p->buf_elems, int(std::max({d[0] * d[1] * (d[2] | 1), d[0] * d[1] * (d[5] | 1),
