@@ -24,9 +24,12 @@
 // The matrix-core variants (MX) form each mode product as 16 x 16 x 4 float
 // products instead (mode_mfma): the factor is the A operand, held in
 // registers, and 16 fibers form the B operand of each tile, read from the
-// same LDS region.  The wave's time per cuboid is mostly the latency of its
-// dependent steps (load X, three products, store Y), so the gain over the
-// vector units is small; the kernel runs as fast as resident waves allow.
+// same LDS region.  Lanes whose output falls outside the result store it to
+// a dump slot in the (unused) factor region instead of being masked off, and
+// Y is assembled in the region in its own layout and then stored in whole
+// 256-byte rows (the region holds J1 J2 J3 values too).  The wave's time per
+// cuboid is mostly the latency and issue of its dependent steps (load X,
+// three products, store Y); the kernel runs as fast as resident waves allow.
 //
 // Work assignment: the plan sorts the cuboids longest first and deals them
 // to the waves of the launch by LPT (each to the wave with the least work so
@@ -199,7 +202,7 @@ __device__ __forceinline__ void mode_any(const T *buf, int NF, int L, const T *U
 template <int KS, int NTM, typename RB, typename OB>
 __device__ __forceinline__ void mode_mfma_body(const float *buf, int NF, int L, const float (&ua)[4], int M, RB rbase,
                                                int rstride, float *lout, float *gout, OB obase, int ostride,
-                                               int lane) {
+                                               int dump, int lane) {
     const int c = lane & 15, g = lane >> 4;
     const int NT = (NF + 15) >> 4;
     int kofs[KS];
@@ -226,15 +229,21 @@ __device__ __forceinline__ void mode_mfma_body(const float *buf, int NF, int L, 
 #pragma unroll
     for (int t = 0; t < NTM; ++t) {
         const int f = t * 16 + c;
-        if (t < NT && f < NF) {
-            const int64_t o = obase(f);
+        if (gout) {
+            if (t < NT && f < NF) {
+                const int64_t o = obase(f);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int j = 4 * g + r;
+                    if (j < M) gout[o + int64_t(j) * ostride] = acc[t][r];
+                }
+            }
+        } else if (t < NT) {   // uniform; lanes past NF or M store to the dump slot
+            const int o = obase(f < NF ? f : NF - 1);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int j = 4 * g + r;
-                if (j < M) {
-                    if (gout) gout[o + int64_t(j) * ostride] = acc[t][r];
-                    else lout[o + j * ostride] = acc[t][r];
-                }
+                lout[f < NF && j < M ? o + j * ostride : dump] = acc[t][r];
             }
         }
     }
@@ -243,11 +252,12 @@ __device__ __forceinline__ void mode_mfma_body(const float *buf, int NF, int L, 
 // mode_mfma_body for runtime L (1..16) and NF (1..256)
 template <typename RB, typename OB>
 __device__ __forceinline__ void mode_mfma(const float *buf, int NF, int L, const float (&ua)[4], int M, RB rbase,
-                                          int rstride, float *lout, float *gout, OB obase, int ostride, int lane) {
+                                          int rstride, float *lout, float *gout, OB obase, int ostride, int dump,
+                                          int lane) {
     const int KS = (L + 3) >> 2, NTQ = (NF + 63) >> 6;
 #define TTM_MX_CASE(ks, ntq)                                                                              \
     case (ks - 1) * 4 + (ntq - 1):                                                                        \
-        mode_mfma_body<ks, 4 * ntq>(buf, NF, L, ua, M, rbase, rstride, lout, gout, obase, ostride, lane); \
+        mode_mfma_body<ks, 4 * ntq>(buf, NF, L, ua, M, rbase, rstride, lout, gout, obase, ostride, dump, lane); \
         break;
     switch ((KS - 1) * 4 + (NTQ - 1)) {
         TTM_MX_CASE(1, 1) TTM_MX_CASE(1, 2) TTM_MX_CASE(1, 3) TTM_MX_CASE(1, 4)
@@ -402,7 +412,7 @@ k_batched(const BatchArgs a, const T *__restrict__ X, const T *__restrict__ Ag, 
         const int SW = J3 | 1;
         auto rb3 = [&](int f) { return f * SX; };
         auto ob3 = [&](int f) { return f * SW; };
-        if constexpr (MX) mode_mfma(buf, I1 * I2, I3, fr[2], J3, rb3, 1, buf, static_cast<T *>(nullptr), ob3, 1, lane);
+        if constexpr (MX) mode_mfma(buf, I1 * I2, I3, fr[2], J3, rb3, 1, buf, static_cast<T *>(nullptr), ob3, 1, -a.fac_elems, lane);
         else mode_any(buf, I1 * I2, I3, fac, P3, J3, rb3, 1, buf, static_cast<T *>(nullptr), ob3, 1, lane);
         wave_sync();
         if constexpr (!MX) {
@@ -414,7 +424,7 @@ k_batched(const BatchArgs a, const T *__restrict__ X, const T *__restrict__ Ag, 
         const float invJ3 = __builtin_amdgcn_rcpf(float(J3));
         auto rb2 = [&](int g) { const int i1 = row_of(g, invJ3); return i1 * I2 * SW + (g - i1 * J3); };
         auto ob2 = [&](int g) { const int i1 = row_of(g, invJ3); return i1 * SV + (g - i1 * J3); };
-        if constexpr (MX) mode_mfma(buf, I1 * J3, I2, fr[1], J2, rb2, SW, buf, static_cast<T *>(nullptr), ob2, J3, lane);
+        if constexpr (MX) mode_mfma(buf, I1 * J3, I2, fr[1], J2, rb2, SW, buf, static_cast<T *>(nullptr), ob2, J3, -a.fac_elems, lane);
         else mode_any(buf, I1 * J3, I2, fac, P2, J2, rb2, SW, buf, static_cast<T *>(nullptr), ob2, J3, lane);
         wave_sync();
         if constexpr (!MX) {
@@ -424,8 +434,19 @@ k_batched(const BatchArgs a, const T *__restrict__ X, const T *__restrict__ Ag, 
         // mode 1: fiber h = (j2, j3) along i1 -> Y[j1][h]
         const int H = J2 * J3;
         auto rb1 = [&](int h) { return h; };
-        if constexpr (MX) mode_mfma(buf, H, I1, fr[0], J1, rb1, SV, buf, Y + d.oy, rb1, H, lane);
-        else mode_any(buf, H, I1, fac, P1, J1, rb1, SV, buf, Y + d.oy, rb1, H, lane);
+        if constexpr (MX) {
+            // Y in its own layout [j1][h] into the region (every tile is
+            // formed before the region is written), then out with whole
+            // 256-byte rows of stores
+            mode_mfma(buf, H, I1, fr[0], J1, rb1, SV, buf, static_cast<T *>(nullptr), rb1, H, -a.fac_elems, lane);
+            wave_sync();
+            const int ny = J1 * H;
+            T *ys = Y + d.oy;
+#pragma unroll 4
+            for (int e = lane; e < ny; e += 64) ys[e] = buf[e];
+        } else {
+            mode_any(buf, H, I1, fac, P1, J1, rb1, SV, buf, Y + d.oy, rb1, H, lane);
+        }
         wave_sync();
     }
 }
@@ -703,7 +724,7 @@ int ttm_batched_plan_create(int64_t count, const int64_t *dims_host, int dtype, 
         p->fac_elems = std::max<int>(p->fac_elems, int(std::max({d[3] * round_up(d[0], 4), d[4] * round_up(d[1], 4),
                                                                   d[5] * round_up(d[2], 4)})));
         p->buf_elems = std::max<int>(p->buf_elems, int(std::max({d[0] * d[1] * (d[2] | 1), d[0] * d[1] * (d[5] | 1),
-                                                                  d[0] * ((d[4] * d[5]) | 1)})));
+                                                                  d[0] * ((d[4] * d[5]) | 1), d[3] * d[4] * d[5]})));
     }
     for (int n = 0; n < 5; ++n) p->totals[n] = o[n];
     // the dot products read up to three rows (of at most 16) past a factor's last
