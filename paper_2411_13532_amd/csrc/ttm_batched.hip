@@ -402,7 +402,8 @@ k_batched(const BatchArgs a, const T *__restrict__ X, const T *__restrict__ Ag, 
             for (int u = 0; u < 16; ++u) {
                 const int e = base + u * 64 + lane;
                 const int f = row_of(e, inv3);
-                if (e < nx) buf[f * SX + (e - f * I3)] = r[u];
+                if constexpr (MX) buf[e < nx ? f * SX + (e - f * I3) : -a.fac_elems] = r[u];   // past X: dump slot
+                else if (e < nx) buf[f * SX + (e - f * I3)] = r[u];
             }
         }
         wave_sync();
