@@ -196,13 +196,14 @@ __device__ __forceinline__ void mode_any(const T *buf, int NF, int L, const T *U
 // from buf[rbase(f) + k * rstride], the fiber and k clamped to valid elements
 // where the factor slot is zero (the value only has to be finite).  Lane l's
 // accumulator element r is D[4 (l / 16) + r][16 t + l % 16], written to
-// out[obase(f) + j * ostride].  Every tile is formed before any output is
-// written, so the outputs may overwrite the fibers (the caller syncs the wave
-// before and after).  Fixed order of the terms.
+// out[obase(f) + j * ostride] in LDS; lanes past NF or M write out[dump]
+// instead (a slot nothing reads), so no store is masked.  Every tile is
+// formed before any output is written, so the outputs may overwrite the
+// fibers (the caller syncs the wave before and after).  Fixed order of the
+// terms.
 template <int KS, int NTM, typename RB, typename OB>
 __device__ __forceinline__ void mode_mfma_body(const float *buf, int NF, int L, const float (&ua)[4], int M, RB rbase,
-                                               int rstride, float *lout, float *gout, OB obase, int ostride,
-                                               int dump, int lane) {
+                                               int rstride, float *out, OB obase, int ostride, int dump, int lane) {
     const int c = lane & 15, g = lane >> 4;
     const int NT = (NF + 15) >> 4;
     int kofs[KS];
@@ -228,22 +229,13 @@ __device__ __forceinline__ void mode_mfma_body(const float *buf, int NF, int L, 
     wave_sync();   // every tile is formed: the outputs may overwrite the fibers
 #pragma unroll
     for (int t = 0; t < NTM; ++t) {
-        const int f = t * 16 + c;
-        if (gout) {
-            if (t < NT && f < NF) {
-                const int64_t o = obase(f);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int j = 4 * g + r;
-                    if (j < M) gout[o + int64_t(j) * ostride] = acc[t][r];
-                }
-            }
-        } else if (t < NT) {   // uniform; lanes past NF or M store to the dump slot
+        if (t < NT) {   // uniform
+            const int f = t * 16 + c;
             const int o = obase(f < NF ? f : NF - 1);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int j = 4 * g + r;
-                lout[f < NF && j < M ? o + j * ostride : dump] = acc[t][r];
+                out[f < NF && j < M ? o + j * ostride : dump] = acc[t][r];
             }
         }
     }
@@ -252,12 +244,11 @@ __device__ __forceinline__ void mode_mfma_body(const float *buf, int NF, int L, 
 // mode_mfma_body for runtime L (1..16) and NF (1..256)
 template <typename RB, typename OB>
 __device__ __forceinline__ void mode_mfma(const float *buf, int NF, int L, const float (&ua)[4], int M, RB rbase,
-                                          int rstride, float *lout, float *gout, OB obase, int ostride, int dump,
-                                          int lane) {
+                                          int rstride, float *out, OB obase, int ostride, int dump, int lane) {
     const int KS = (L + 3) >> 2, NTQ = (NF + 63) >> 6;
 #define TTM_MX_CASE(ks, ntq)                                                                              \
     case (ks - 1) * 4 + (ntq - 1):                                                                        \
-        mode_mfma_body<ks, 4 * ntq>(buf, NF, L, ua, M, rbase, rstride, lout, gout, obase, ostride, dump, lane); \
+        mode_mfma_body<ks, 4 * ntq>(buf, NF, L, ua, M, rbase, rstride, out, obase, ostride, dump, lane);  \
         break;
     switch ((KS - 1) * 4 + (NTQ - 1)) {
         TTM_MX_CASE(1, 1) TTM_MX_CASE(1, 2) TTM_MX_CASE(1, 3) TTM_MX_CASE(1, 4)
@@ -413,7 +404,7 @@ k_batched(const BatchArgs a, const T *__restrict__ X, const T *__restrict__ Ag, 
         const int SW = J3 | 1;
         auto rb3 = [&](int f) { return f * SX; };
         auto ob3 = [&](int f) { return f * SW; };
-        if constexpr (MX) mode_mfma(buf, I1 * I2, I3, fr[2], J3, rb3, 1, buf, static_cast<T *>(nullptr), ob3, 1, -a.fac_elems, lane);
+        if constexpr (MX) mode_mfma(buf, I1 * I2, I3, fr[2], J3, rb3, 1, buf, ob3, 1, -a.fac_elems, lane);
         else mode_any(buf, I1 * I2, I3, fac, P3, J3, rb3, 1, buf, static_cast<T *>(nullptr), ob3, 1, lane);
         wave_sync();
         if constexpr (!MX) {
@@ -425,7 +416,7 @@ k_batched(const BatchArgs a, const T *__restrict__ X, const T *__restrict__ Ag, 
         const float invJ3 = __builtin_amdgcn_rcpf(float(J3));
         auto rb2 = [&](int g) { const int i1 = row_of(g, invJ3); return i1 * I2 * SW + (g - i1 * J3); };
         auto ob2 = [&](int g) { const int i1 = row_of(g, invJ3); return i1 * SV + (g - i1 * J3); };
-        if constexpr (MX) mode_mfma(buf, I1 * J3, I2, fr[1], J2, rb2, SW, buf, static_cast<T *>(nullptr), ob2, J3, -a.fac_elems, lane);
+        if constexpr (MX) mode_mfma(buf, I1 * J3, I2, fr[1], J2, rb2, SW, buf, ob2, J3, -a.fac_elems, lane);
         else mode_any(buf, I1 * J3, I2, fac, P2, J2, rb2, SW, buf, static_cast<T *>(nullptr), ob2, J3, lane);
         wave_sync();
         if constexpr (!MX) {
@@ -439,7 +430,7 @@ k_batched(const BatchArgs a, const T *__restrict__ X, const T *__restrict__ Ag, 
             // Y in its own layout [j1][h] into the region (every tile is
             // formed before the region is written), then out with whole
             // 256-byte rows of stores
-            mode_mfma(buf, H, I1, fr[0], J1, rb1, SV, buf, static_cast<T *>(nullptr), rb1, H, -a.fac_elems, lane);
+            mode_mfma(buf, H, I1, fr[0], J1, rb1, SV, buf, rb1, H, -a.fac_elems, lane);
             wave_sync();
             const int ny = J1 * H;
             T *ys = Y + d.oy;
